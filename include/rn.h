@@ -1,0 +1,159 @@
+/*
+ * rn.h -- C ABI of the MI355X (gfx950) tau-leaping parameter-sweep library.
+ *
+ * The library runs many independent stochastic simulations of one mass-action
+ * reaction network, one per parameterization (kinetic constants and initial
+ * amounts differ between simulations: paper, Aims and motivation section).  The
+ * state of a simulation is the vector of molecule counts per species, and a
+ * reaction firing changes it by the reaction's stoichiometry (paper, Methods
+ * section).  Each simulation is advanced by Cao-Gillespie-Petzold tau-leaping
+ * (Y. Cao, D. T. Gillespie, L. R. Petzold, J. Chem. Phys. 124, 044109 (2006))
+ * with critical reactions (J. Chem. Phys. 123, 054104 (2005)) and bursts of
+ * exact SSA events (Gillespie, J. Phys. Chem. 81, 2340 (1977)).
+ *
+ * Conventions
+ *  - Every function returns RN_OK (0) or a negative RN_E_* code, except
+ *    rn_free_network (void) and rn_strerror (string).
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the device that was current when the network was loaded.
+ *  - Nothing here takes or returns a framework type; all sizes are int32/int64.
+ */
+#ifndef RN_H
+#define RN_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RN_OK 0
+#define RN_E_INVALID_ARG (-1)     /* null pointer, bad size, bad times, bad option      */
+#define RN_E_INVALID_NETWORK (-2) /* species index out of range, coefficient <= 0 ...   */
+#define RN_E_UNSUPPORTED (-3)     /* a reaction with three or more reactant molecules   */
+#define RN_E_NOMEM (-4)           /* host or device allocation failed                   */
+#define RN_E_DEVICE (-5)          /* a HIP call failed; rn_last_device_error() names it */
+
+/* Per-trajectory status bits (stats[t][3]); never a call error. */
+#define RN_ST_ABSORBED 1u /* total propensity reached 0; later samples repeat the state     */
+#define RN_ST_MAXSTEPS 2u /* leaps + SSA events + rejections reached max_steps              */
+#define RN_ST_OVERFLOW 4u /* a count would exceed 2^31-1; later samples repeat the last state */
+
+#define RN_METHOD_TAULEAP 0 /* CGP tau-leaping with critical reactions and SSA bursts */
+#define RN_METHOD_SSA 1     /* exact SSA events only (Gillespie direct method)        */
+
+#define RN_FP64 0 /* all of the method's arithmetic in double precision */
+
+/*
+ * Network description (host memory, caller-owned, copied by rn_load_network).
+ * Reaction j has reactants react_species/coeff[react_ptr[j] .. react_ptr[j+1])
+ * and products prod_species/coeff[prod_ptr[j] .. prod_ptr[j+1]) (compressed
+ * rows, n_reactions+1 offsets each).  A species listed twice in one list has
+ * its coefficients added.  Mass-action order (sum of reactant coefficients)
+ * must be 0, 1 or 2; coefficients must lie in [1, 2^20].  A reaction may have no
+ * products (degradation) or no reactants (source).
+ */
+typedef struct {
+  int32_t n_species, n_reactions;
+  const int32_t *react_ptr, *react_species, *react_coeff;
+  const int32_t *prod_ptr, *prod_species, *prod_coeff;
+} rn_network_desc;
+
+typedef struct rn_network rn_network; /* opaque; immutable after load */
+
+/*
+ * Validate and preprocess a network (paper, Methods section: species counts and
+ * the reactions that change them) and upload its tables to the current HIP
+ * device.  On success *out owns a library handle (free with rn_free_network).
+ * Errors: RN_E_INVALID_ARG (null pointer, n_species or n_reactions <= 0,
+ * offsets not non-decreasing), RN_E_INVALID_NETWORK (species index out of
+ * range, coefficient out of [1, 2^20]), RN_E_UNSUPPORTED (order > 2),
+ * RN_E_NOMEM, RN_E_DEVICE.  *out is untouched on error.
+ */
+int rn_load_network(const rn_network_desc *desc, rn_network **out);
+
+/* Release a handle and its device tables (null is ignored).  The caller must
+ * make sure no sweep using it is still running. */
+void rn_free_network(rn_network *net);
+
+/* Number of species / reactions of a loaded network (-1 for a null handle). */
+int32_t rn_network_species(const rn_network *net);
+int32_t rn_network_reactions(const rn_network *net);
+
+/*
+ * Equally spaced observation times of X(t) on [0, t_end] (paper, Methods
+ * section: sample paths observed through time): out[s] = s * t_end / (n - 1)
+ * for s < n-1 and out[n-1] = t_end exactly; n = 1 gives {t_end}.  `out` is a
+ * host array of n_points doubles.  Errors: RN_E_INVALID_ARG when out is null,
+ * n_points < 1, or t_end is negative or not finite.
+ */
+int rn_sample_times(double t_end, int32_t n_points, double *out);
+
+/*
+ * One parameter sweep: n_traj independent trajectories of the network, each
+ * with its own rate constants (and optionally its own initial counts), all
+ * observed at the same sample times.
+ *
+ *  traj_offset  global id of local trajectory 0; trajectory t draws from the
+ *               Philox4x32-10 stream keyed by `seed` with counter word 0 equal
+ *               to traj_offset + t, so a sweep split into ranges reproduces the
+ *               unsplit one exactly.  traj_offset + n_traj <= 2^32.
+ *  rates        device, double, rates[j * rates_ld + t] (reaction-major,
+ *               trajectory-minor), rates_ld >= n_traj; finite and >= 0.
+ *  x0           device, int32: x0[i] (x0_ld == 0, broadcast to every
+ *               trajectory) or x0[i * x0_ld + t] (x0_ld >= n_traj); >= 0.
+ *  times        device, double[n_times], finite, >= 0, strictly increasing.
+ *  out          device, int32, out[(s * n_species + i) * out_ld + t] receives
+ *               X_i(times[s]) of trajectory t; out_ld >= n_traj.
+ *  stats        device, uint64[n_traj][4]: accepted leaps, SSA events,
+ *               rejected leaps, status bits (RN_ST_*).
+ *  eps          leap-condition tolerance (0 < eps < 1); n_c critical threshold
+ *               (0 <= n_c <= 2^20); ssa_factor: leap only when
+ *               tau' >= ssa_factor / a0 (>= 0); ssa_burst: exact events per
+ *               burst (>= 1); max_steps: per-trajectory cap on leaps + SSA
+ *               events + rejections (>= 1).
+ *  method       RN_METHOD_TAULEAP or RN_METHOD_SSA; precision RN_FP64.
+ *
+ * Buffers are caller-owned and must not overlap.  The call only validates the
+ * arguments it can see on the host and enqueues kernels on `hip_stream` (a
+ * hipStream_t; null = the default stream); it returns before they finish and
+ * allocates nothing.  Per-trajectory conditions go to stats[t][3].  Errors:
+ * RN_E_INVALID_ARG, RN_E_DEVICE.  Concurrent sweeps on one handle are allowed.
+ */
+typedef struct {
+  int64_t n_traj;
+  int64_t traj_offset;
+  const double *rates;
+  int64_t rates_ld;
+  const int32_t *x0;
+  int64_t x0_ld;
+  const double *times;
+  int32_t n_times;
+  int32_t *out;
+  int64_t out_ld;
+  uint64_t *stats;
+  uint64_t seed;
+  double eps;
+  int32_t n_c;
+  double ssa_factor;
+  int32_t ssa_burst;
+  uint64_t max_steps;
+  int32_t method;
+  int32_t precision;
+} rn_sweep_args;
+
+/* Defaults: eps 0.03, n_c 10, ssa_factor 10, ssa_burst 100, max_steps 1e8,
+ * tau-leaping, FP64 (CGP 2006's recommended switch constants). */
+void rn_sweep_args_init(rn_sweep_args *args);
+
+int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream);
+
+/* Message for an RN_* code (static storage). */
+const char *rn_strerror(int code);
+
+/* The hipError_t of the most recent RN_E_DEVICE in this thread (0 if none). */
+int rn_last_device_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

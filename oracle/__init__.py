@@ -1,0 +1,161 @@
+"""Plain FP64 CPU oracle for tau-leaping parameter sweeps (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY.  Imported by the test suite, by the package smoke
+check and by the benchmark's CPU-baseline leg; the product path never imports
+it.  It shares no code with the HIP path: its own C source computes the
+network tables, the Philox stream, the samplers and the method's steps.
+
+The method is Cao-Gillespie-Petzold tau-leaping with critical reactions and an
+exact-SSA fallback (Cao, Gillespie, Petzold, J. Chem. Phys. 124, 044109, 2006)
+applied to the stochastic model of the paper's Methods section.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+_lib = None
+
+ST_ABSORBED, ST_MAXSTEPS, ST_OVERFLOW = 1, 2, 4
+
+
+class _NetDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("react_ptr", C.c_void_p), ("react_species", C.c_void_p), ("react_coeff", C.c_void_p),
+                ("prod_ptr", C.c_void_p), ("prod_species", C.c_void_p), ("prod_coeff", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("eps", C.c_double), ("n_c", C.c_int32),
+                ("ssa_factor", C.c_double), ("ssa_burst", C.c_int32),
+                ("max_steps", C.c_uint64), ("method", C.c_int32)]
+
+
+OPS_FIELDS = ["leaps", "ssa_events", "rejections", "prop_evals", "crit_tests", "tau_terms",
+              "tau_species", "philox_blocks", "inv_draws", "inv_iters", "ptrs_draws",
+              "ptrs_iters", "ptrs_log_tests", "exp_draws", "select_terms", "update_terms"]
+
+
+class _Ops(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in OPS_FIELDS]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_u53.restype = C.c_double
+        L.orc_poisson.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32,
+                                  C.c_void_p]
+        L.orc_poisson.restype = C.c_int64
+        L.orc_poisson_many.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_int32, C.c_int64,
+                                       C.c_void_p]
+        L.orc_poisson_many.restype = None
+        L.orc_run.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_run.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, o.ctypes.data)
+    return o
+
+
+def u53(hi, lo):
+    return lib().orc_u53(int(hi), int(lo))
+
+
+def poisson(lam, seed, traj, n, j):
+    return int(lib().orc_poisson(float(lam), int(seed), int(traj), int(n), int(j), None))
+
+
+def poisson_many(lam, seed, n, j=0, n0=0):
+    out = np.zeros(int(n), dtype=np.int64)
+    lib().orc_poisson_many(float(lam), int(seed), int(n0), int(j), int(n), out.ctypes.data)
+    return out
+
+
+def _desc(net):
+    arrs = {k: np.ascontiguousarray(v, dtype=np.int32) for k, v in net.csr().items()}
+    d = _NetDesc(net.n_species, net.n_reactions,
+                 arrs["react_ptr"].ctypes.data, arrs["react_species"].ctypes.data,
+                 arrs["react_coeff"].ctypes.data, arrs["prod_ptr"].ctypes.data,
+                 arrs["prod_species"].ctypes.data, arrs["prod_coeff"].ctypes.data)
+    return d, arrs
+
+
+def run(net, rates, x0, times, *, seed, eps=0.03, n_c=10, ssa_factor=10.0, ssa_burst=100,
+        max_steps=10**8, method="tauleap", traj_range=None, threads=1, counters=False):
+    """Simulate trajectories ``traj_range = (a, b)`` (default: all columns of ``rates``).
+
+    Returns ``(out, stats, ops)``: ``out`` int32 ``[S][N][b-a]``, ``stats`` uint64
+    ``[b-a][4]`` (leaps, ssa events, rejections, status bits) and ``ops`` a dict
+    of operation counts (or None).
+    """
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    M, T = rates.shape
+    if M != net.n_reactions:
+        raise ValueError("rates must have one row per reaction")
+    a, b = traj_range if traj_range is not None else (0, T)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    if x0.ndim == 2 and x0.shape[1] != T:
+        raise ValueError("per-trajectory x0 must have one column per trajectory")
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    S, N = len(times), net.n_species
+    n = b - a
+    out = np.zeros((S, N, n), dtype=np.int32)
+    stats = np.zeros((n, 4), dtype=np.uint64)
+    desc, keep = _desc(net)
+    par = _Params(int(seed), float(eps), int(n_c), float(ssa_factor), int(ssa_burst),
+                  int(max_steps), 1 if method == "ssa" else 0)
+    L = lib()
+    chunks = []
+    nth = max(1, min(int(threads), n)) if n > 0 else 1
+    bounds = np.linspace(0, n, nth + 1).astype(np.int64)
+    ops_list = [_Ops() for _ in range(nth)]
+
+    def work(ci):
+        lo, hi = int(bounds[ci]), int(bounds[ci + 1])
+        if hi <= lo:
+            return 0
+        rp = rates.ctypes.data + 8 * (a + lo)
+        if x0.ndim == 2:
+            xp, xld = x0.ctypes.data + 4 * (a + lo), T
+        else:
+            xp, xld = x0.ctypes.data, 0
+        # out[(s*N+i)*n + t] with t offset by lo
+        op = out.ctypes.data + 4 * lo
+        sp = stats.ctypes.data + 8 * 4 * lo
+        return L.orc_run(C.byref(desc), rp, T, xp, xld, times.ctypes.data, S, a + lo, hi - lo,
+                         op, n, sp, C.byref(par), C.byref(ops_list[ci]) if counters else None)
+
+    if nth == 1:
+        rcs = [work(0)]
+    else:
+        with ThreadPoolExecutor(nth) as ex:
+            rcs = list(ex.map(work, range(nth)))
+    for rc in rcs:
+        if rc != 0:
+            raise RuntimeError(f"oracle error {rc}")
+    del chunks, keep
+    ops = None
+    if counters:
+        ops = {f: sum(getattr(o, f) for o in ops_list) for f in OPS_FIELDS}
+    return out, stats, ops

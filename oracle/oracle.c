@@ -120,7 +120,10 @@ int64_t orc_poisson(double lam, uint64_t seed, uint32_t traj, uint32_t n, int32_
     double rhs = -lam + kf * loglam - lgamma(kf + 1.0);
     if (lhs <= rhs) return (int64_t)(kf < K_CLAMP ? kf : K_CLAMP);
   }
-  return (int64_t)floor(lam);
+  {
+    double kf = floor(lam);
+    return (int64_t)(kf < K_CLAMP ? kf : K_CLAMP);
+  }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -283,6 +286,7 @@ static int ssa_events(traj_state *T, int64_t count) {
     while (T->s < T->S && T->times[T->s] < tn) record(T, T->s++);
     if (T->s == T->S) return BURST_DONE;
     int j = pick_reaction(T, u2 * a0, NULL);
+    if (j < 0) { T->status |= ORC_ST_ABSORBED; fill_rest(T); return BURST_DONE; }
     int ovf = 0;
     for (int i = 0; i < g->N; ++i) {
       int v = g->nu[(size_t)j * g->N + i];
@@ -393,6 +397,7 @@ static void simulate(traj_state *T) {
       }
       if (fire) {
         int jc = pick_reaction(T, orc_u53(ev[2], ev[3]) * a0c, T->crit);
+        if (jc < 0) { T->status |= ORC_ST_ABSORBED; fill_rest(T); return; }
         T->k[jc] = 1;
       }
 

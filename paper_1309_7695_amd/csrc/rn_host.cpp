@@ -1,0 +1,314 @@
+// rn_host.cpp -- C ABI of the sweep library: argument validation, network
+// preprocessing into packed device tables, and kernel launch selection.
+//
+// Preprocessing follows the method's needs (CGP 2006): rate laws of order <= 2,
+// net stoichiometric changes nu_ij = products - reactants, the consumed-reactant
+// lists that define critical reactions, and for every reactant species the
+// highest reaction order and homodimer flag that fix its g_i factor.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "rn.h"
+#include "rn_kernel.h"
+
+struct rn_network {
+  int32_t N = 0, M = 0;
+  int device = 0;
+  void* dbuf = nullptr;
+  size_t bytes = 0;
+  rn::DevNet dev{};
+};
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int device_error(hipError_t e) {
+  g_last_hip = (int)e;
+  return RN_E_DEVICE;
+}
+
+constexpr int32_t kMaxCoeff = 1 << 20;
+
+// Host image of the tables before upload.
+struct HostTables {
+  std::vector<rn::RateLaw> law;
+  std::vector<int32_t> nu_ptr, cons_ptr, col_ptr;
+  std::vector<int2> nu_ent, cons_ent, rs_ent, col_ent;
+  std::vector<uint32_t> nu_abs;
+  std::vector<rn::TauSpecies> rs;
+  int32_t crit_words = 0;
+};
+
+int build_tables(const rn_network_desc* d, HostTables& T) {
+  const int32_t N = d->n_species, M = d->n_reactions;
+  if (!d->react_ptr || !d->prod_ptr) return RN_E_INVALID_ARG;
+  if (d->react_ptr[0] != 0 || d->prod_ptr[0] != 0) return RN_E_INVALID_ARG;
+  for (int32_t j = 0; j < M; ++j)
+    if (d->react_ptr[j + 1] < d->react_ptr[j] || d->prod_ptr[j + 1] < d->prod_ptr[j])
+      return RN_E_INVALID_ARG;
+  if ((d->react_ptr[M] > 0 && (!d->react_species || !d->react_coeff)) ||
+      (d->prod_ptr[M] > 0 && (!d->prod_species || !d->prod_coeff)))
+    return RN_E_INVALID_ARG;
+
+  std::vector<int32_t> hor(N, 0), dimer(N, 0);
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> nu(M);  // per reaction (species, nu)
+  T.law.resize(M);
+  T.nu_abs.resize(M);
+  for (int32_t j = 0; j < M; ++j) {
+    std::map<int32_t, int64_t> r, net;
+    int64_t order = 0;
+    for (int32_t e = d->react_ptr[j]; e < d->react_ptr[j + 1]; ++e) {
+      const int32_t s = d->react_species[e], c = d->react_coeff[e];
+      if (s < 0 || s >= N || c < 1 || c > kMaxCoeff) return RN_E_INVALID_NETWORK;
+      r[s] += c;
+      order += c;
+    }
+    for (int32_t e = d->prod_ptr[j]; e < d->prod_ptr[j + 1]; ++e) {
+      const int32_t s = d->prod_species[e], c = d->prod_coeff[e];
+      if (s < 0 || s >= N || c < 1 || c > kMaxCoeff) return RN_E_INVALID_NETWORK;
+      net[s] += c;
+    }
+    if (order > 2) return RN_E_UNSUPPORTED;
+    for (auto& kv : r) net[kv.first] -= kv.second;
+    rn::RateLaw L{N, N, 0, 0};
+    if (order == 1) {
+      L.ia = r.begin()->first;
+    } else if (order == 2) {
+      if (r.size() == 2) {
+        L.ia = r.begin()->first;
+        L.ib = std::next(r.begin())->first;
+      } else {
+        L.ia = L.ib = r.begin()->first;
+        L.db = -1;
+        L.dimer = 1;
+      }
+    }
+    T.law[j] = L;
+    for (auto& kv : r) {
+      hor[kv.first] = std::max<int32_t>(hor[kv.first], (int32_t)order);
+      if (kv.second == 2) dimer[kv.first] = 1;
+    }
+    int64_t sum_abs = 0;
+    for (auto& kv : net) {
+      if (kv.second == 0) continue;
+      if (kv.second > INT32_MAX || kv.second < -INT32_MAX) return RN_E_INVALID_NETWORK;
+      nu[j].push_back({kv.first, (int32_t)kv.second});
+      sum_abs += kv.second < 0 ? -kv.second : kv.second;
+    }
+    if (sum_abs > INT32_MAX) return RN_E_INVALID_NETWORK;
+    T.nu_abs[j] = (uint32_t)sum_abs;
+  }
+
+  T.nu_ptr.assign(1, 0);
+  T.cons_ptr.assign(1, 0);
+  std::vector<std::vector<int2>> col(N);
+  for (int32_t j = 0; j < M; ++j) {
+    for (auto& sv : nu[j]) {
+      T.nu_ent.push_back(make_int2(sv.first, sv.second));
+      if (sv.second < 0) T.cons_ent.push_back(make_int2(sv.first, -sv.second));
+      col[sv.first].push_back(make_int2(j, sv.second));  // ascending j
+    }
+    T.nu_ptr.push_back((int32_t)T.nu_ent.size());
+    T.cons_ptr.push_back((int32_t)T.cons_ent.size());
+  }
+  T.col_ptr.assign(1, 0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (auto& e : col[i]) T.col_ent.push_back(e);
+    T.col_ptr.push_back((int32_t)T.col_ent.size());
+  }
+  for (int32_t i = 0; i < N; ++i) {
+    if (hor[i] == 0) continue;
+    rn::TauSpecies ts;
+    ts.species = i;
+    ts.gkind = hor[i] == 1 ? 1 : (dimer[i] ? 3 : 2);
+    ts.begin = (int32_t)T.rs_ent.size();
+    for (auto& e : col[i]) T.rs_ent.push_back(e);
+    ts.end = (int32_t)T.rs_ent.size();
+    T.rs.push_back(ts);
+  }
+  T.crit_words = (M + 31) / 32;
+  return RN_OK;
+}
+
+// Appends a host array to a packed image, 16-byte aligned; returns its offset.
+template <class V>
+size_t pack(std::vector<unsigned char>& img, const V& v) {
+  size_t off = (img.size() + 15) & ~(size_t)15;
+  const size_t nb = v.size() * sizeof(typename V::value_type);
+  img.resize(off + std::max<size_t>(nb, 16), 0);
+  if (nb) std::memcpy(img.data() + off, v.data(), nb);
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rn_strerror(int code) {
+  switch (code) {
+    case RN_OK: return "ok";
+    case RN_E_INVALID_ARG: return "invalid argument";
+    case RN_E_INVALID_NETWORK: return "invalid network description";
+    case RN_E_UNSUPPORTED: return "unsupported network (reaction order above 2, or too large)";
+    case RN_E_NOMEM: return "out of memory";
+    case RN_E_DEVICE: return "HIP device error";
+    default: return "unknown error";
+  }
+}
+
+int rn_last_device_error(void) { return g_last_hip; }
+
+int rn_sample_times(double t_end, int32_t n_points, double* out) {
+  if (!out || n_points < 1 || !std::isfinite(t_end) || t_end < 0.0) return RN_E_INVALID_ARG;
+  if (n_points == 1) {
+    out[0] = t_end;
+    return RN_OK;
+  }
+  const double den = (double)(n_points - 1);
+  for (int32_t s = 0; s < n_points - 1; ++s) out[s] = ((double)s * t_end) / den;
+  out[n_points - 1] = t_end;
+  return RN_OK;
+}
+
+void rn_sweep_args_init(rn_sweep_args* a) {
+  if (!a) return;
+  std::memset(a, 0, sizeof(*a));
+  a->eps = 0.03;
+  a->n_c = 10;
+  a->ssa_factor = 10.0;
+  a->ssa_burst = 100;
+  a->max_steps = 100000000ull;
+  a->method = RN_METHOD_TAULEAP;
+  a->precision = RN_FP64;
+}
+
+int32_t rn_network_species(const rn_network* net) { return net ? net->N : -1; }
+int32_t rn_network_reactions(const rn_network* net) { return net ? net->M : -1; }
+
+int rn_load_network(const rn_network_desc* desc, rn_network** out) {
+  if (!desc || !out) return RN_E_INVALID_ARG;
+  if (desc->n_species <= 0 || desc->n_reactions <= 0) return RN_E_INVALID_ARG;
+  if (desc->n_species > (1 << 20) || desc->n_reactions > (1 << 20)) return RN_E_UNSUPPORTED;
+  HostTables T;
+  int rc;
+  try {
+    rc = build_tables(desc, T);
+  } catch (const std::bad_alloc&) {
+    return RN_E_NOMEM;
+  }
+  if (rc != RN_OK) return rc;
+
+  std::vector<unsigned char> img;
+  const size_t o_law = pack(img, T.law), o_nu_ptr = pack(img, T.nu_ptr),
+               o_nu_ent = pack(img, T.nu_ent), o_cons_ptr = pack(img, T.cons_ptr),
+               o_cons_ent = pack(img, T.cons_ent), o_nu_abs = pack(img, T.nu_abs),
+               o_rs = pack(img, T.rs), o_rs_ent = pack(img, T.rs_ent),
+               o_col_ptr = pack(img, T.col_ptr), o_col_ent = pack(img, T.col_ent);
+
+  rn_network* net = new (std::nothrow) rn_network;
+  if (!net) return RN_E_NOMEM;
+  net->N = desc->n_species;
+  net->M = desc->n_reactions;
+  hipError_t e = hipGetDevice(&net->device);
+  if (e != hipSuccess) { delete net; return device_error(e); }
+  e = hipMalloc(&net->dbuf, img.size());
+  if (e != hipSuccess) { delete net; return e == hipErrorOutOfMemory ? RN_E_NOMEM : device_error(e); }
+  e = hipMemcpy(net->dbuf, img.data(), img.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(net->dbuf); delete net; return device_error(e); }
+  net->bytes = img.size();
+  unsigned char* b = (unsigned char*)net->dbuf;
+  rn::DevNet& D = net->dev;
+  D.N = net->N;
+  D.M = net->M;
+  D.n_rs = (int32_t)T.rs.size();
+  D.crit_words = T.crit_words;
+  D.law = (const rn::RateLaw*)(b + o_law);
+  D.nu_ptr = (const int32_t*)(b + o_nu_ptr);
+  D.nu_ent = (const int2*)(b + o_nu_ent);
+  D.cons_ptr = (const int32_t*)(b + o_cons_ptr);
+  D.cons_ent = (const int2*)(b + o_cons_ent);
+  D.nu_abs = (const uint32_t*)(b + o_nu_abs);
+  D.rs = (const rn::TauSpecies*)(b + o_rs);
+  D.rs_ent = (const int2*)(b + o_rs_ent);
+  D.col_ptr = (const int32_t*)(b + o_col_ptr);
+  D.col_ent = (const int2*)(b + o_col_ent);
+  *out = net;
+  return RN_OK;
+}
+
+void rn_free_network(rn_network* net) {
+  if (!net) return;
+  if (net->dbuf) (void)hipFree(net->dbuf);
+  delete net;
+}
+
+int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
+  if (!net || !a) return RN_E_INVALID_ARG;
+  if (a->n_traj < 0 || a->traj_offset < 0 || a->traj_offset + a->n_traj > (int64_t)1 << 32)
+    return RN_E_INVALID_ARG;
+  if (a->n_times < 1) return RN_E_INVALID_ARG;
+  if (!(a->eps > 0.0) || !std::isfinite(a->eps)) return RN_E_INVALID_ARG;
+  if (a->n_c < 0 || a->n_c > (1 << 20)) return RN_E_INVALID_ARG;
+  if (!(a->ssa_factor >= 0.0)) return RN_E_INVALID_ARG;
+  if (a->ssa_burst < 1 || a->max_steps < 1) return RN_E_INVALID_ARG;
+  if (a->method != RN_METHOD_TAULEAP && a->method != RN_METHOD_SSA) return RN_E_INVALID_ARG;
+  if (a->precision != RN_FP64) return RN_E_INVALID_ARG;
+  if (a->n_traj == 0) return RN_OK;
+  if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats) return RN_E_INVALID_ARG;
+  if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj) return RN_E_INVALID_ARG;
+  if (a->x0_ld != 0 && a->x0_ld < a->n_traj) return RN_E_INVALID_ARG;
+
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e);
+  if (dev != net->device) return RN_E_INVALID_ARG;
+  int max_lds = 0, n_cu = 0;
+  e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return device_error(e);
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return device_error(e);
+
+  const size_t per_lane = rn::lds_words_per_lane(net->N, net->M) * sizeof(int32_t);
+  rn::LaunchCfg cfg{};
+  cfg.rate_segs = 0;
+  // 256 lanes per workgroup (one wave per SIMD of a CU) when the sweep fills the
+  // chip; otherwise single-wave workgroups spread over more CUs.
+  if (a->n_traj >= (int64_t)256 * n_cu && per_lane * 256 <= (size_t)max_lds) cfg.wg = 256;
+  else cfg.wg = 64;
+  cfg.lds_bytes = per_lane * cfg.wg;
+  if (cfg.lds_bytes > (size_t)max_lds) return RN_E_UNSUPPORTED;
+
+  rn::SweepParams p{};
+  p.net = net->dev;
+  p.rates = a->rates;
+  p.rates_ld = a->rates_ld;
+  p.x0 = a->x0;
+  p.x0_ld = a->x0_ld;
+  p.times = a->times;
+  p.n_times = a->n_times;
+  p.out = a->out;
+  p.out_ld = a->out_ld;
+  p.stats = a->stats;
+  p.n_traj = a->n_traj;
+  p.traj_offset = (uint32_t)a->traj_offset;
+  p.key0 = (uint32_t)a->seed;
+  p.key1 = (uint32_t)(a->seed >> 32);
+  p.eps = a->eps;
+  p.n_c = a->n_c;
+  p.ssa_factor = a->ssa_factor;
+  p.ssa_burst = a->ssa_burst;
+  p.max_steps = a->max_steps;
+  p.method = a->method;
+  e = rn::launch_sweep(p, cfg, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return device_error(e);
+  return RN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// rn_kernel.h -- packed device tables and kernel parameters of the sweep kernels.
+//
+// Internal to the library (host code in rn_host.cpp fills these, the kernels in
+// rn_sweep.hip read them).  Every table is read with wave-uniform indices, so the
+// kernels fetch them through the scalar data cache.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rn {
+
+// One reaction's rate law: a_j = c_j * s_j * (x[ia] * (x[ib] + db)), where the
+// pseudo-species N always holds 1 (so order 0 uses ia = ib = N, order 1 uses
+// ib = N), a homodimer uses ib = ia, db = -1, s_j = 1/2, and every other case
+// has db = 0, s_j = 1.
+struct RateLaw {
+  int32_t ia, ib, db, dimer;
+};
+
+// Leap-condition entry of one reactant species (CGP 2006): its species index,
+// the g-rule (1: highest order 1; 2: highest order 2, never two molecules of it
+// in one reaction; 3: highest order 2 with a homodimer), and its range in the
+// species-major stoichiometry list.
+struct TauSpecies {
+  int32_t species, gkind, begin, end;
+};
+
+struct DevNet {
+  int32_t N, M, n_rs, crit_words;
+  const RateLaw* law;        // [M]
+  const int32_t* nu_ptr;     // [M+1] reaction-major net changes
+  const int2* nu_ent;        // {species, nu_ij}, nu_ij != 0
+  const int32_t* cons_ptr;   // [M+1] consumed reactants (nu_ij < 0)
+  const int2* cons_ent;      // {species, |nu_ij|}
+  const uint32_t* nu_abs;    // [M] sum_i |nu_ij|
+  const TauSpecies* rs;      // [n_rs] reactant species, ascending
+  const int2* rs_ent;        // {j, nu_ij} per reactant species, ascending j
+  const int32_t* col_ptr;    // [N+1] species-major net changes (all species)
+  const int2* col_ent;       // {j, nu_ij}, ascending j
+};
+
+struct SweepParams {
+  DevNet net;
+  const double* rates;
+  int64_t rates_ld;
+  const int32_t* x0;
+  int64_t x0_ld;
+  const double* times;
+  int32_t n_times;
+  int32_t* out;
+  int64_t out_ld;
+  uint64_t* stats;
+  int64_t n_traj;
+  uint32_t traj_offset;
+  uint32_t key0, key1;
+  double eps;
+  int32_t n_c;
+  double ssa_factor;
+  int32_t ssa_burst;
+  uint64_t max_steps;
+  int32_t method;
+};
+
+// Launch configuration chosen by the host.
+struct LaunchCfg {
+  int wg;          // lanes (= trajectories) per workgroup: 64 or 256
+  int rate_segs;   // 0: rates read from memory; k: held in k registers segments of 16
+  size_t lds_bytes;
+};
+
+// Kernel LDS bytes per lane: two count buffers of N+1 words and the
+// critical-reaction bit words.
+inline size_t lds_words_per_lane(int N, int M) {
+  return 2 * (size_t)(N + 1) + (size_t)((M + 31) / 32);
+}
+
+hipError_t launch_sweep(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
+
+}  // namespace rn

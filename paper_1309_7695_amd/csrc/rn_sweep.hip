@@ -1,0 +1,454 @@
+// rn_sweep.hip -- gfx950 kernels: one wave64 lane per trajectory of a parameter
+// sweep, each advanced by Cao-Gillespie-Petzold tau-leaping (J. Chem. Phys. 124,
+// 044109, 2006) with critical reactions (J. Chem. Phys. 123, 054104, 2005) and
+// bursts of exact SSA events (Gillespie's direct method, 1977).  The model is the
+// paper's (Methods section): X(t) counts molecules per species and every firing
+// adds the reaction's stoichiometric vector.
+//
+// Layout
+//  * Counts: LDS, lane-minor.  Each lane owns two buffers of N+1 words (current
+//    state and leap candidate; word N is the constant 1 used by the rate laws)
+//    plus ceil(M/32) critical-reaction bit words.  Lanes never share LDS words,
+//    so the kernel has no barriers.
+//  * Network tables: read-only global memory, always at wave-uniform indices
+//    (scalar loads).
+//  * Rates [M][T] and samples [S][N][T]: trajectory-minor global arrays, so a
+//    wave's 64 lanes touch 64 consecutive words.
+//
+// Per-lane control is a small state machine (decide / SSA event / leap attempt).
+// Each loop iteration runs every phase that some lane of the wave needs, masked
+// to those lanes.  Counter-based random numbers make each trajectory's result
+// independent of how its steps interleave with other lanes'.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rn_kernel.h"
+
+namespace rn {
+namespace {
+
+// Philox counter layout: (trajectory id, attempt counter n, slot, stream).
+constexpr uint32_t kStreamEvent = 0u;  // slot 0: words 0-1 waiting time, 2-3 reaction pick
+constexpr uint32_t kStreamFirst = 1u;  // slot j/2: words 2(j%2), 2(j%2)+1 = inversion uniform of j
+constexpr uint32_t kStreamPtrs = 2u;   // slot j, stream 2+r: round r of the PTRS sampler for j
+constexpr int kInvMax = 100;           // inversion search cap
+constexpr uint32_t kPtrsMax = 1000u;   // PTRS round cap
+constexpr double kClamp = 2147483648.0;  // draws are clamped to 2^31
+
+enum : int { kDecide = 0, kSsa = 1, kLeap = 2, kDone = 3 };
+
+constexpr uint32_t kStAbsorbed = 1u, kStMaxSteps = 2u, kStOverflow = 4u;
+
+struct Words {
+  uint32_t w0, w1, w2, w3;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The key schedule is
+// wave-uniform, so it stays in scalar registers.
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = y0;
+    c2 = y2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// Uniform on [0,1) with 53 random bits: the top 53 bits of (hi:lo) times 2^-53.
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+  const uint64_t z = (((uint64_t)hi << 32) | (uint64_t)lo) >> 11;
+  return (double)z * 0x1p-53;
+}
+
+// Poisson(lam) for 0 < lam < 10: walk the CDF from k = 0 with one uniform,
+// p_k = p_{k-1} * (lam * (1/k)).
+__device__ __forceinline__ uint32_t poisson_inversion(double lam, double u) {
+  double pk = exp(-lam);
+  double F = pk;
+  int k = 0;
+  while (u > F && k < kInvMax) {
+    k = k + 1;
+    pk = pk * (lam * (1.0 / (double)k));
+    F = F + pk;
+  }
+  return (uint32_t)k;
+}
+
+__device__ __forceinline__ uint32_t clamp_draw(double kf) {
+  return kf < kClamp ? (uint32_t)kf : 0x80000000u;
+}
+
+// Poisson(lam) for lam >= 10: Hoermann's transformed rejection with squeeze
+// (PTRS, Insurance: Math. & Econ. 12 (1993) 39); round r draws its (U, V) pair
+// from its own Philox block.
+__device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_t n, uint32_t j,
+                                              uint32_t k0, uint32_t k1) {
+  const double smu = sqrt(lam);
+  const double b = 0.931 + 2.53 * smu;
+  const double a = -0.059 + 0.02483 * b;
+  const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+  const double vr = 0.9277 - 3.6224 / (b - 2.0);
+  const double loglam = log(lam);
+  for (uint32_t r = 0; r < kPtrsMax; ++r) {
+    const Words w = philox10(traj, n, j, kStreamPtrs + r, k0, k1);
+    const double U = u53(w.w0, w.w1) - 0.5;
+    const double V = u53(w.w2, w.w3);
+    const double us = 0.5 - fabs(U);
+    const double kf = floor((2.0 * a / us + b) * U + lam + 0.43);
+    if (us >= 0.07 && V <= vr) return clamp_draw(kf);
+    if (kf < 0.0 || (us < 0.013 && V > us)) continue;
+    const double lhs = log(V * inv_alpha / (a / (us * us) + b));
+    const double rhs = -lam + kf * loglam - lgamma(kf + 1.0);
+    if (lhs <= rhs) return clamp_draw(kf);
+  }
+  return clamp_draw(floor(lam));
+}
+
+__device__ __forceinline__ uint32_t poisson(double lam, uint32_t hi, uint32_t lo, uint32_t traj,
+                                            uint32_t n, uint32_t j, uint32_t k0, uint32_t k1) {
+  if (!(lam > 0.0)) return 0u;
+  if (lam < 10.0) return poisson_inversion(lam, u53(hi, lo));
+  return poisson_ptrs(lam, traj, n, j, k0, k1);
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
+  extern __shared__ int32_t lds[];
+  const DevNet& g = p.net;
+  const int N = g.N, M = g.M, NP1 = N + 1;
+  const int tid = (int)threadIdx.x;
+  const int64_t tl = (int64_t)blockIdx.x * WG + tid;
+  const bool valid = tl < p.n_traj;
+  const uint32_t traj = p.traj_offset + (uint32_t)tl;
+  const uint32_t k0 = p.key0, k1 = p.key1;
+  const int S = p.n_times;
+  const double* __restrict__ times = p.times;
+
+  int32_t* const lane = lds + tid;
+  int32_t* xc = lane;                 // current counts
+  int32_t* xn = lane + NP1 * WG;      // leap candidate
+  int32_t* const crit = lane + 2 * NP1 * WG;
+  const double* const crate = p.rates + (valid ? tl : 0);
+  const int64_t rld = p.rates_ld;
+
+  for (int i = 0; i < N; ++i) {
+    int32_t v = 0;
+    if (valid) v = p.x0_ld ? p.x0[(int64_t)i * p.x0_ld + tl] : p.x0[i];
+    xc[i * WG] = v;
+  }
+  xc[N * WG] = 1;
+  xn[N * WG] = 1;
+
+  double t = 0.0, tau_p = 0.0, a0 = 0.0;
+  uint32_t n = 0, burst_left = 0, status = 0;
+  uint64_t leaps = 0, ssa = 0, rej = 0;
+  int s = 0;
+  int mode = valid ? (p.method == 1 ? kSsa : kDecide) : kDone;
+  const bool ssa_only = p.method == 1;
+
+  auto rate = [&](int j) -> double { return crate[(int64_t)j * rld]; };
+  // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
+  auto prop = [&](int j, double c) -> double {
+    const RateLaw L = g.law[j];
+    const double A = (double)xc[L.ia * WG];
+    const double B = (double)(xc[L.ib * WG] + L.db);
+    double h = A * B;
+    if (L.dimer) h = 0.5 * h;
+    return c * h;
+  };
+  auto critbit = [&](int j) -> bool {
+    return ((uint32_t)crit[(j >> 5) * WG] >> (j & 31)) & 1u;
+  };
+  // Only lanes that own a trajectory ever write: padding lanes of the last
+  // workgroup (tl >= n_traj) would alias other trajectories' columns.
+  auto record = [&](int si) {
+    if (!valid) return;
+    int32_t* o = p.out + (int64_t)si * N * p.out_ld + tl;
+    for (int i = 0; i < N; ++i) o[(int64_t)i * p.out_ld] = xc[i * WG];
+  };
+  auto finish = [&](uint32_t why) {
+    status |= why;
+    while (s < S) record(s++);
+    mode = kDone;
+  };
+  auto steps = [&]() -> uint64_t { return leaps + ssa + rej; };
+  // Net change of reaction j applied k times to buffer x.
+  auto apply = [&](int32_t* x, int j, int32_t k) {
+    const int e1 = g.nu_ptr[j + 1];
+    for (int e = g.nu_ptr[j]; e < e1; ++e) {
+      const int2 en = g.nu_ent[e];
+      x[en.x * WG] += k * en.y;
+    }
+  };
+
+  if (valid) {
+    while (s < S && times[s] <= t) record(s++);
+    if (s == S) mode = kDone;
+  }
+
+  for (;;) {
+    if (!__any(mode != kDone)) break;
+
+    // ---------------- one exact SSA event ----------------
+    if (mode == kSsa) {
+      do {
+        if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
+        double sum = 0.0;
+        for (int j = 0; j < M; ++j) sum = sum + prop(j, rate(j));
+        if (sum == 0.0) { finish(kStAbsorbed); break; }
+        const Words w = philox10(traj, n, 0u, kStreamEvent, k0, k1);
+        const double tau = -log(1.0 - u53(w.w0, w.w1)) / sum;
+        const double tn = t + tau;
+        while (s < S && times[s] < tn) record(s++);
+        if (s == S) { mode = kDone; break; }
+        const double r = u53(w.w2, w.w3) * sum;
+        double acc = 0.0;
+        int pick = -1, last = -1;
+        for (int j = 0; j < M; ++j) {
+          if (!__any(pick < 0)) break;
+          if (pick < 0) {
+            const double a = prop(j, rate(j));
+            acc = acc + a;
+            if (a > 0.0) last = j;
+            if (r < acc) pick = j;
+          }
+        }
+        if (pick < 0) pick = last;
+        if (pick < 0) { finish(kStAbsorbed); break; }
+        bool bad = false;
+        for (int e = g.nu_ptr[pick]; e < g.nu_ptr[pick + 1]; ++e) {
+          const int2 en = g.nu_ent[e];
+          const int64_t y = (int64_t)xc[en.x * WG] + en.y;
+          if (y > INT32_MAX || y < 0) bad = true;
+        }
+        if (bad) { finish(kStOverflow); break; }
+        for (int e = g.nu_ptr[pick]; e < g.nu_ptr[pick + 1]; ++e) {
+          const int2 en = g.nu_ent[e];
+          xc[en.x * WG] += en.y;
+        }
+        t = tn;
+        n = n + 1;
+        ssa = ssa + 1;
+        while (s < S && times[s] <= t) record(s++);
+        if (s == S) { mode = kDone; break; }
+        if (!ssa_only && --burst_left == 0) mode = kDecide;
+      } while (false);
+    }
+
+    // ---------------- decide: propensities, critical set, tau' ----------------
+    if (mode == kDecide) {
+      do {
+        if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
+        double sum = 0.0;
+        for (int w = 0; w < g.crit_words; ++w) {
+          uint32_t bits = 0;
+          const int jend = min(M, 32 * w + 32);
+          for (int j = 32 * w; j < jend; ++j) {
+            const double a = prop(j, rate(j));
+            sum = sum + a;
+            if (a > 0.0) {
+              bool cr = false;
+              const int e1 = g.cons_ptr[j + 1];
+              for (int e = g.cons_ptr[j]; e < e1; ++e) {
+                const int2 ce = g.cons_ent[e];
+                if ((int64_t)xc[ce.x * WG] < (int64_t)p.n_c * ce.y) cr = true;
+              }
+              if (cr) bits |= 1u << (j - 32 * w);
+            }
+          }
+          crit[w * WG] = (int32_t)bits;
+        }
+        a0 = sum;
+        if (sum == 0.0) { finish(kStAbsorbed); break; }
+        double tp = __builtin_inf();
+        for (int r = 0; r < g.n_rs; ++r) {
+          const TauSpecies ts = g.rs[r];
+          double mu = 0.0, sig = 0.0;
+          for (int e = ts.begin; e < ts.end; ++e) {
+            const int2 en = g.rs_ent[e];
+            if (critbit(en.x)) continue;
+            const double a = prop(en.x, rate(en.x));
+            mu = mu + (double)en.y * a;
+            sig = sig + (double)(en.y * en.y) * a;
+          }
+          const int32_t xi = xc[ts.species * WG];
+          double bnd = 1.0;
+          if (xi > 1) {
+            const double gi = ts.gkind == 1 ? 1.0
+                              : ts.gkind == 2 ? 2.0
+                                              : 2.0 + 1.0 / (double)(xi - 1);
+            bnd = p.eps * (double)xi / gi;
+            if (bnd < 1.0) bnd = 1.0;
+          }
+          if (mu != 0.0) { const double q = bnd / fabs(mu); if (q < tp) tp = q; }
+          if (sig != 0.0) { const double q = (bnd * bnd) / sig; if (q < tp) tp = q; }
+        }
+        tau_p = tp;
+        mode = kLeap;
+      } while (false);
+    }
+
+    // ---------------- one leap attempt ----------------
+    if (mode == kLeap) {
+      do {
+        if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
+        if (tau_p < p.ssa_factor / a0) {
+          mode = kSsa;
+          burst_left = (uint32_t)p.ssa_burst;
+          break;
+        }
+        double a0c = 0.0;
+        for (int w = 0; w < g.crit_words; ++w) {
+          const uint32_t bits = (uint32_t)crit[w * WG];
+          if (!__any(bits != 0u)) continue;
+          const int jend = min(M, 32 * w + 32);
+          for (int j = 32 * w; j < jend; ++j)
+            if ((bits >> (j - 32 * w)) & 1u) a0c = a0c + prop(j, rate(j));
+        }
+        Words ev = {0u, 0u, 0u, 0u};
+        double tau_c = __builtin_inf();
+        if (a0c > 0.0) {
+          ev = philox10(traj, n, 0u, kStreamEvent, k0, k1);
+          tau_c = -log(1.0 - u53(ev.w0, ev.w1)) / a0c;
+        }
+        const double delta = times[s] - t;
+        const bool fire = (tau_c <= tau_p) && (tau_c <= delta);
+        const double tau = fire ? tau_c : (tau_p < delta ? tau_p : delta);
+
+        int32_t xmax = 0;
+        for (int i = 0; i < N; ++i) {
+          const int32_t v = xc[i * WG];
+          xn[i * WG] = v;
+          xmax = max(xmax, v);
+        }
+        uint64_t kabs = 0;
+        for (int j = 0; j < M; j += 2) {
+          const bool two = j + 1 < M;
+          double l0 = 0.0, l1 = 0.0;
+          if (!critbit(j)) l0 = prop(j, rate(j)) * tau;
+          if (two && !critbit(j + 1)) l1 = prop(j + 1, rate(j + 1)) * tau;
+          Words w = {0u, 0u, 0u, 0u};
+          if ((l0 > 0.0 && l0 < 10.0) || (l1 > 0.0 && l1 < 10.0))
+            w = philox10(traj, n, (uint32_t)(j >> 1), kStreamFirst, k0, k1);
+          const uint32_t d0 = poisson(l0, w.w0, w.w1, traj, n, (uint32_t)j, k0, k1);
+          const uint32_t d1 = poisson(l1, w.w2, w.w3, traj, n, (uint32_t)(j + 1), k0, k1);
+          if (__any(d0 != 0u)) apply(xn, j, (int32_t)d0);
+          if (two && __any(d1 != 0u)) apply(xn, j + 1, (int32_t)d1);
+          kabs += (uint64_t)d0 * g.nu_abs[j];
+          if (two) kabs += (uint64_t)d1 * g.nu_abs[j + 1];
+        }
+        int jc = -1;
+        if (fire) {
+          const double r = u53(ev.w2, ev.w3) * a0c;
+          double acc = 0.0;
+          int last = -1;
+          for (int j = 0; j < M; ++j) {
+            if (!__any(jc < 0)) break;
+            if (jc < 0 && critbit(j)) {
+              const double a = prop(j, rate(j));
+              acc = acc + a;
+              if (a > 0.0) last = j;
+              if (r < acc) jc = j;
+            }
+          }
+          if (jc < 0) jc = last;
+          if (jc < 0) { finish(kStAbsorbed); break; }
+          apply(xn, jc, 1);
+          kabs += g.nu_abs[jc];
+        }
+
+        bool neg = false, big = false;
+        if ((uint64_t)xmax + kabs <= (uint64_t)INT32_MAX) {
+          // no partial sum can leave the int32 range: the candidate is exact
+          for (int i = 0; i < N; ++i) neg = neg || (xn[i * WG] < 0);
+        } else {
+          // exact 64-bit evaluation, species by species, redrawing each k_j
+          for (int i = 0; i < N; ++i) {
+            int64_t acc = xc[i * WG];
+            for (int e = g.col_ptr[i]; e < g.col_ptr[i + 1]; ++e) {
+              const int2 en = g.col_ent[e];
+              const int j = en.x;
+              int64_t kj;
+              if (critbit(j)) {
+                kj = (fire && j == jc) ? 1 : 0;
+              } else {
+                const double lam = prop(j, rate(j)) * tau;
+                Words w = {0u, 0u, 0u, 0u};
+                if (lam > 0.0 && lam < 10.0)
+                  w = philox10(traj, n, (uint32_t)(j >> 1), kStreamFirst, k0, k1);
+                const uint32_t hi = (j & 1) ? w.w2 : w.w0;
+                const uint32_t lo = (j & 1) ? w.w3 : w.w1;
+                kj = poisson(lam, hi, lo, traj, n, (uint32_t)j, k0, k1);
+              }
+              acc += kj * (int64_t)en.y;
+            }
+            if (acc < 0) neg = true;
+            else if (acc > INT32_MAX) big = true;
+          }
+        }
+        if (neg) {
+          tau_p = tau_p * 0.5;
+          n = n + 1;
+          rej = rej + 1;
+          break;  // stays in leap mode
+        }
+        if (big) { finish(kStOverflow); break; }
+        int32_t* tmp = xc;
+        xc = xn;
+        xn = tmp;
+        if (tau == delta) t = times[s];
+        else t = t + tau;
+        n = n + 1;
+        leaps = leaps + 1;
+        while (s < S && times[s] <= t) record(s++);
+        if (s == S) { mode = kDone; break; }
+        mode = kDecide;
+      } while (false);
+    }
+  }
+
+  if (valid) {
+    uint64_t* st = p.stats + tl * 4;
+    st[0] = leaps;
+    st[1] = ssa;
+    st[2] = rej;
+    st[3] = status;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream) {
+  const int64_t blocks = (p.n_traj + cfg.wg - 1) / cfg.wg;
+  if (blocks <= 0) return hipSuccess;
+  hipError_t err = hipSuccess;
+  switch (cfg.wg) {
+    case 64:
+      err = hipFuncSetAttribute((const void*)sweep_kernel<64>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(sweep_kernel<64>, dim3((unsigned)blocks), dim3(64), cfg.lds_bytes, stream, p);
+      break;
+    case 256:
+      err = hipFuncSetAttribute((const void*)sweep_kernel<256>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(sweep_kernel<256>, dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, stream,
+                         p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rn

@@ -1,0 +1,237 @@
+"""ctypes binding of the C ABI in ``include/rn.h`` (``librn.so``).
+
+Argument marshalling only: every step of the simulation runs in the library's
+HIP kernels.  PyTorch supplies device memory and the HIP stream.  When the
+library has not been built this module raises instead of falling back to
+anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librn.so")
+
+RN_OK = 0
+RN_E_INVALID_ARG = -1
+RN_E_INVALID_NETWORK = -2
+RN_E_UNSUPPORTED = -3
+RN_E_NOMEM = -4
+RN_E_DEVICE = -5
+ST_ABSORBED, ST_MAXSTEPS, ST_OVERFLOW = 1, 2, 4
+METHOD_TAULEAP, METHOD_SSA = 0, 1
+FP64 = 0
+
+EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
+           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_strerror",
+           "rn_last_device_error"]
+
+
+class NetworkDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("react_ptr", C.c_void_p), ("react_species", C.c_void_p),
+                ("react_coeff", C.c_void_p), ("prod_ptr", C.c_void_p),
+                ("prod_species", C.c_void_p), ("prod_coeff", C.c_void_p)]
+
+
+class SweepArgs(C.Structure):
+    _fields_ = [("n_traj", C.c_int64), ("traj_offset", C.c_int64),
+                ("rates", C.c_void_p), ("rates_ld", C.c_int64),
+                ("x0", C.c_void_p), ("x0_ld", C.c_int64),
+                ("times", C.c_void_p), ("n_times", C.c_int32),
+                ("out", C.c_void_p), ("out_ld", C.c_int64),
+                ("stats", C.c_void_p), ("seed", C.c_uint64),
+                ("eps", C.c_double), ("n_c", C.c_int32), ("ssa_factor", C.c_double),
+                ("ssa_burst", C.c_int32), ("max_steps", C.c_uint64),
+                ("method", C.c_int32), ("precision", C.c_int32)]
+
+
+class RNError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().rn_strerror(code).decode()
+        if code == RN_E_DEVICE:
+            msg += f" (hipError {lib().rn_last_device_error()})"
+        super().__init__(f"{what}: {msg} [{code}]" if what else f"{msg} [{code}]")
+
+
+_lib = None
+
+
+def lib():
+    """Load ``librn.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1309_7695_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.rn_load_network.argtypes = [C.POINTER(NetworkDesc), C.POINTER(C.c_void_p)]
+        L.rn_load_network.restype = C.c_int
+        L.rn_free_network.argtypes = [C.c_void_p]
+        L.rn_free_network.restype = None
+        L.rn_network_species.argtypes = [C.c_void_p]
+        L.rn_network_species.restype = C.c_int32
+        L.rn_network_reactions.argtypes = [C.c_void_p]
+        L.rn_network_reactions.restype = C.c_int32
+        L.rn_sample_times.argtypes = [C.c_double, C.c_int32, C.c_void_p]
+        L.rn_sample_times.restype = C.c_int
+        L.rn_sweep_args_init.argtypes = [C.POINTER(SweepArgs)]
+        L.rn_sweep_args_init.restype = None
+        L.rn_sweep.argtypes = [C.c_void_p, C.POINTER(SweepArgs), C.c_void_p]
+        L.rn_sweep.restype = C.c_int
+        L.rn_strerror.argtypes = [C.c_int]
+        L.rn_strerror.restype = C.c_char_p
+        L.rn_last_device_error.argtypes = []
+        L.rn_last_device_error.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != RN_OK:
+        raise RNError(rc, what)
+
+
+def sample_times(t_end, n_points):
+    out = np.zeros(max(int(n_points), 1), dtype=np.float64)
+    _check(lib().rn_sample_times(float(t_end), int(n_points), out.ctypes.data), "rn_sample_times")
+    return out
+
+
+def network_desc(net):
+    """(NetworkDesc, keep-alive arrays) for a ``gen.Network``-like object or a
+    dict of CSR arrays plus ``n_species``."""
+    if isinstance(net, dict):
+        arrs = {k: np.ascontiguousarray(net[k], dtype=np.int32) for k in
+                ("react_ptr", "react_species", "react_coeff", "prod_ptr", "prod_species",
+                 "prod_coeff")}
+        ns = int(net["n_species"])
+    else:
+        arrs = {k: np.ascontiguousarray(v, dtype=np.int32) for k, v in net.csr().items()}
+        ns = int(net.n_species)
+    nr = len(arrs["react_ptr"]) - 1
+    d = NetworkDesc(ns, nr, *(arrs[k].ctypes.data if arrs[k].size else None for k in
+                              ("react_ptr", "react_species", "react_coeff", "prod_ptr",
+                               "prod_species", "prod_coeff")))
+    return d, arrs
+
+
+class Network:
+    """A network loaded onto the current HIP device (``rn_load_network``)."""
+
+    def __init__(self, net):
+        d, keep = network_desc(net)
+        h = C.c_void_p()
+        _check(lib().rn_load_network(C.byref(d), C.byref(h)), "rn_load_network")
+        self._h = h
+        self.n_species = lib().rn_network_species(h)
+        self.n_reactions = lib().rn_network_reactions(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().rn_free_network(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
+          n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
+          stream=None):
+    """Enqueue ``rn_sweep`` on ``stream`` (default: torch's current stream).
+
+    ``rates`` float64 [M][>=T] (row stride = ld), ``x0`` int32 [N] or [N][>=T],
+    ``times`` float64 [S], ``out`` int32 [S][N][>=T] (last dim stride = ld),
+    ``stats`` uint64/int64 [T][4]; all CUDA (HIP) tensors on the network's
+    device.  T is taken from ``stats``.  Returns immediately."""
+    import torch
+
+    T = int(stats.shape[0])
+    for name, t in (("rates", rates), ("x0", x0), ("times", times), ("out", out),
+                    ("stats", stats)):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+    if rates.dtype != torch.float64 or times.dtype != torch.float64:
+        raise TypeError("rates and times must be float64")
+    if x0.dtype != torch.int32 or out.dtype != torch.int32:
+        raise TypeError("x0 and out must be int32")
+    if stats.dtype not in (torch.int64, torch.uint64) or tuple(stats.shape) != (T, 4) or \
+            not stats.is_contiguous():
+        raise TypeError("stats must be a contiguous 64-bit [T][4] tensor")
+    if rates.dim() != 2 or rates.stride(1) != 1 or rates.shape[0] != net.n_reactions:
+        raise ValueError("rates must be [M][T] with unit trajectory stride")
+    if out.dim() != 3 or out.stride(2) != 1 or out.shape[1] != net.n_species or \
+            out.stride(0) != out.shape[1] * out.stride(1) or out.shape[0] != times.numel():
+        raise ValueError("out must be [S][N][T] with unit trajectory stride")
+    if not times.is_contiguous():
+        raise ValueError("times must be contiguous")
+    if rates.shape[1] < T or out.shape[2] < T:
+        raise ValueError("rates and out need at least one column per trajectory")
+    if x0.dim() == 1:
+        x0_ld = 0
+        if x0.numel() != net.n_species or not x0.is_contiguous():
+            raise ValueError("x0 must have one entry per species")
+    else:
+        if x0.stride(1) != 1 or x0.shape[0] != net.n_species or x0.shape[1] < T:
+            raise ValueError("per-trajectory x0 must be [N][T] with unit trajectory stride")
+        x0_ld = x0.stride(0)
+    a = SweepArgs()
+    lib().rn_sweep_args_init(C.byref(a))
+    a.n_traj = T
+    a.traj_offset = int(traj_offset)
+    a.rates, a.rates_ld = rates.data_ptr(), rates.stride(0)
+    a.x0, a.x0_ld = x0.data_ptr(), x0_ld
+    a.times, a.n_times = times.data_ptr(), times.numel()
+    a.out, a.out_ld = out.data_ptr(), out.stride(1)
+    a.stats = stats.data_ptr()
+    a.seed = int(seed) & (2**64 - 1)
+    a.eps, a.n_c, a.ssa_factor = float(eps), int(n_c), float(ssa_factor)
+    a.ssa_burst, a.max_steps, a.method, a.precision = int(ssa_burst), int(max_steps), \
+        int(method), FP64
+    if stream is None:
+        stream = torch.cuda.current_stream(rates.device)
+    _check(lib().rn_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)), "rn_sweep")
+
+
+def validate_times(times):
+    t = np.asarray(times, dtype=np.float64)
+    if t.ndim != 1 or t.size < 1 or not np.all(np.isfinite(t)) or np.any(t < 0) or \
+            np.any(np.diff(t) <= 0):
+        raise ValueError("times must be finite, non-negative and strictly increasing")
+    return t
+
+
+def run(net_desc, rates, x0, times, *, seed, device="cuda", method="tauleap", **kw):
+    """Host-array convenience: upload, sweep, synchronize, download.
+
+    Returns ``(out [S][N][T] int32, stats [T][4] uint64)`` as numpy arrays."""
+    import torch
+
+    times = validate_times(times)
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    M, T = rates.shape
+    dev = torch.device(device)
+    net = net_desc if isinstance(net_desc, Network) else Network(net_desc)
+    S, N = len(times), net.n_species
+    r_d = torch.from_numpy(rates).to(dev)
+    x_d = torch.from_numpy(x0).to(dev)
+    t_d = torch.from_numpy(times).to(dev)
+    o_d = torch.empty((S, N, T), dtype=torch.int32, device=dev)
+    s_d = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    sweep(net, r_d, x_d, t_d, o_d, s_d, seed=seed,
+          method=METHOD_SSA if method == "ssa" else METHOD_TAULEAP, **kw)
+    torch.cuda.synchronize(dev)
+    return o_d.cpu().numpy(), s_d.cpu().numpy().view(np.uint64)

@@ -13,8 +13,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=off: every floating-point operation is rounded once, in the
 # written order (no fused multiply-add), as the method's arithmetic is specified.
 # -packed-fp32-ops: no packed FP32 instructions are generated.
+# promote-alloca-to-vector-limit: lets the per-lane rate vectors (up to 8 x 16
+# doubles) stay in VGPRs instead of being demoted to scratch memory.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-promote-alloca-to-vector-limit=4096",
          "-Wno-unused-command-line-argument"]
 
 

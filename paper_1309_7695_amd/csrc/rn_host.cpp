@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -36,6 +37,18 @@ int device_error(hipError_t e) {
 
 constexpr int32_t kMaxCoeff = 1 << 20;
 
+// Wave scheduling knob (fraction of lanes that must wait before the leap-side
+// phases run).  RN_SCHED_THETA overrides it for tuning; results never depend on it.
+float sched_theta() {
+  static const float theta = [] {
+    const char* s = std::getenv("RN_SCHED_THETA");
+    if (!s) return 0.5f;
+    const float v = std::strtof(s, nullptr);
+    return (v >= 0.0f && v <= 1.0f) ? v : 0.5f;
+  }();
+  return theta;
+}
+
 // Host image of the tables before upload.
 struct HostTables {
   std::vector<rn::RateLaw> law;
@@ -43,6 +56,7 @@ struct HostTables {
   std::vector<int2> nu_ent, cons_ent, rs_ent, col_ent;
   std::vector<uint32_t> nu_abs;
   std::vector<rn::TauSpecies> rs;
+  std::vector<double> log_fact;
   int32_t crit_words = 0;
 };
 
@@ -134,6 +148,8 @@ int build_tables(const rn_network_desc* d, HostTables& T) {
     T.rs.push_back(ts);
   }
   T.crit_words = (M + 31) / 32;
+  T.log_fact.resize(rn::kLogFactTable);
+  for (int k = 0; k < rn::kLogFactTable; ++k) T.log_fact[k] = std::lgamma((double)k + 1.0);
   return RN_OK;
 }
 
@@ -210,7 +226,8 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
                o_nu_ent = pack(img, T.nu_ent), o_cons_ptr = pack(img, T.cons_ptr),
                o_cons_ent = pack(img, T.cons_ent), o_nu_abs = pack(img, T.nu_abs),
                o_rs = pack(img, T.rs), o_rs_ent = pack(img, T.rs_ent),
-               o_col_ptr = pack(img, T.col_ptr), o_col_ent = pack(img, T.col_ent);
+               o_col_ptr = pack(img, T.col_ptr), o_col_ent = pack(img, T.col_ent),
+               o_log_fact = pack(img, T.log_fact);
 
   rn_network* net = new (std::nothrow) rn_network;
   if (!net) return RN_E_NOMEM;
@@ -239,6 +256,7 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
   D.rs_ent = (const int2*)(b + o_rs_ent);
   D.col_ptr = (const int32_t*)(b + o_col_ptr);
   D.col_ent = (const int2*)(b + o_col_ent);
+  D.log_fact = (const double*)(b + o_log_fact);
   *out = net;
   return RN_OK;
 }
@@ -277,7 +295,7 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
 
   const size_t per_lane = rn::lds_words_per_lane(net->N, net->M) * sizeof(int32_t);
   rn::LaunchCfg cfg{};
-  cfg.rate_segs = 0;
+  cfg.rate_segs = net->M <= 16 * rn::kMaxRateSegs ? (net->M + 15) / 16 : 0;
   // 256 lanes per workgroup (one wave per SIMD of a CU) when the sweep fills the
   // chip; otherwise single-wave workgroups spread over more CUs.
   if (a->n_traj >= (int64_t)256 * n_cu && per_lane * 256 <= (size_t)max_lds) cfg.wg = 256;
@@ -306,6 +324,7 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   p.ssa_burst = a->ssa_burst;
   p.max_steps = a->max_steps;
   p.method = a->method;
+  p.theta = sched_theta();
   e = rn::launch_sweep(p, cfg, (hipStream_t)hip_stream);
   if (e != hipSuccess) return device_error(e);
   return RN_OK;

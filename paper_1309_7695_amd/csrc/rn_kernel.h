@@ -37,7 +37,10 @@ struct DevNet {
   const int2* rs_ent;        // {j, nu_ij} per reactant species, ascending j
   const int32_t* col_ptr;    // [N+1] species-major net changes (all species)
   const int2* col_ent;       // {j, nu_ij}, ascending j
+  const double* log_fact;    // [kLogFactTable] log(k!) for small k
 };
+
+constexpr int kLogFactTable = 1024;
 
 struct SweepParams {
   DevNet net;
@@ -59,17 +62,23 @@ struct SweepParams {
   int32_t ssa_burst;
   uint64_t max_steps;
   int32_t method;
+  // Leap-side phases run when at least this fraction of the wave's active lanes
+  // waits for them (or no lane is in an SSA burst).  Scheduling only: results do
+  // not depend on it.
+  float theta;
 };
 
 // Launch configuration chosen by the host.
 struct LaunchCfg {
   int wg;          // lanes (= trajectories) per workgroup: 64 or 256
-  int rate_segs;   // 0: rates read from memory; k: held in k registers segments of 16
+  int rate_segs;   // 0: rates read from memory; k: held in k register vectors of 16
   size_t lds_bytes;
 };
 
 // Kernel LDS bytes per lane: two count buffers of N+1 words and the
 // critical-reaction bit words.
+constexpr int kMaxRateSegs = 8;
+
 inline size_t lds_words_per_lane(int N, int M) {
   return 2 * (size_t)(N + 1) + (size_t)((M + 31) / 32);
 }

@@ -87,17 +87,30 @@ __device__ __forceinline__ uint32_t clamp_draw(double kf) {
   return kf < kClamp ? (uint32_t)kf : 0x80000000u;
 }
 
+// log(k!) for a non-negative integer k held in a double: the host-built table
+// below kLogFactTable, else Stirling's series for log Gamma(x), x = k + 1, to the
+// x^-5 term (the first omitted term is below 1e-18 for x >= 1024).
+__device__ __forceinline__ double log_factorial(double kf, const double* table) {
+  if (kf < (double)kLogFactTable) return table[(int)kf];
+  const double x = kf + 1.0;
+  const double r = 1.0 / x;
+  const double r2 = r * r;
+  const double series = r * (1.0 / 12.0 - r2 * (1.0 / 360.0 - r2 * (1.0 / 1260.0)));
+  return (x - 0.5) * log(x) - x + 0.91893853320467274178 + series;
+}
+
 // Poisson(lam) for lam >= 10: Hoermann's transformed rejection with squeeze
 // (PTRS, Insurance: Math. & Econ. 12 (1993) 39); round r draws its (U, V) pair
 // from its own Philox block.
 __device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_t n, uint32_t j,
-                                              uint32_t k0, uint32_t k1) {
+                                              uint32_t k0, uint32_t k1, const double* lfact) {
   const double smu = sqrt(lam);
   const double b = 0.931 + 2.53 * smu;
   const double a = -0.059 + 0.02483 * b;
   const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
   const double vr = 0.9277 - 3.6224 / (b - 2.0);
   const double loglam = log(lam);
+#pragma unroll 1
   for (uint32_t r = 0; r < kPtrsMax; ++r) {
     const Words w = philox10(traj, n, j, kStreamPtrs + r, k0, k1);
     const double U = u53(w.w0, w.w1) - 0.5;
@@ -107,20 +120,46 @@ __device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_
     if (us >= 0.07 && V <= vr) return clamp_draw(kf);
     if (kf < 0.0 || (us < 0.013 && V > us)) continue;
     const double lhs = log(V * inv_alpha / (a / (us * us) + b));
-    const double rhs = -lam + kf * loglam - lgamma(kf + 1.0);
+    const double rhs = -lam + kf * loglam - log_factorial(kf, lfact);
     if (lhs <= rhs) return clamp_draw(kf);
   }
   return clamp_draw(floor(lam));
 }
 
 __device__ __forceinline__ uint32_t poisson(double lam, uint32_t hi, uint32_t lo, uint32_t traj,
-                                            uint32_t n, uint32_t j, uint32_t k0, uint32_t k1) {
+                                            uint32_t n, uint32_t j, uint32_t k0, uint32_t k1,
+                                            const double* lfact) {
   if (!(lam > 0.0)) return 0u;
   if (lam < 10.0) return poisson_inversion(lam, u53(hi, lo));
-  return poisson_ptrs(lam, traj, n, j, k0, k1);
+  return poisson_ptrs(lam, traj, n, j, k0, k1, lfact);
 }
 
-template <int WG>
+// Network tables are read-only for the whole kernel and indexed wave-uniformly;
+// reading them through the constant address space lets the compiler use scalar
+// loads (a divergent index still falls back to a vector load).
+typedef const int32_t __attribute__((address_space(4)))* const_i32_ptr;
+__device__ __forceinline__ int32_t cld(const void* base, int64_t i) {
+  return ((const_i32_ptr)base)[i];
+}
+__device__ __forceinline__ int2 cld2(const int2* base, int64_t i) {
+  return make_int2(cld(base, 2 * i), cld(base, 2 * i + 1));
+}
+__device__ __forceinline__ RateLaw law_at(const RateLaw* base, int j) {
+  return {cld(base, 4 * j), cld(base, 4 * j + 1), cld(base, 4 * j + 2), cld(base, 4 * j + 3)};
+}
+__device__ __forceinline__ TauSpecies rs_at(const TauSpecies* base, int r) {
+  return {cld(base, 4 * r), cld(base, 4 * r + 1), cld(base, 4 * r + 2), cld(base, 4 * r + 3)};
+}
+
+typedef double v16d __attribute__((ext_vector_type(16)));
+
+// Segment list: rates live in up to eight 16-element register vectors.
+#define RN_SEGS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+// WG lanes per workgroup.  NSEG > 0: the lane's rate constants are held in NSEG
+// register vectors of 16 doubles (M <= 16*NSEG), read with wave-uniform indices
+// (VGPR indexing mode); NSEG == 0: they are read from the rates array.
+template <int WG, int NSEG>
 __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   extern __shared__ int32_t lds[];
   const DevNet& g = p.net;
@@ -140,6 +179,57 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   const double* const crate = p.rates + (valid ? tl : 0);
   const int64_t rld = p.rates_ld;
 
+#define RN_DECL(K) v16d c##K = {};
+  RN_SEGS(RN_DECL)
+#undef RN_DECL
+#define RN_LOAD(K)                                                   \
+  if constexpr (K < NSEG) {                                          \
+    _Pragma("unroll") for (int e = 0; e < 16; ++e) {                 \
+      const int j = K * 16 + e;                                      \
+      c##K[e] = (valid && j < M) ? crate[(int64_t)j * rld] : 0.0;    \
+    }                                                                \
+  }
+  RN_SEGS(RN_LOAD)
+#undef RN_LOAD
+
+  // f(j, c_j) for j = 0..M-1 in order, stopping when f returns false.
+  auto each_rate = [&](auto&& f) {
+    if constexpr (NSEG == 0) {
+      for (int j = 0; j < M; ++j)
+        if (!f(j, crate[(int64_t)j * rld])) return;
+    } else {
+#define RN_EACH(K)                                                   \
+      if constexpr (K < NSEG) {                                      \
+        const int cnt = min(16, M - K * 16);                         \
+        for (int e = 0; e < cnt; ++e)                                \
+          if (!f(K * 16 + e, c##K[e])) return;                       \
+      }
+      RN_SEGS(RN_EACH)
+#undef RN_EACH
+    }
+  };
+  // c_j for one wave-uniform j.
+  auto rate_at = [&](int j) -> double {
+    if constexpr (NSEG == 0) {
+      return crate[(int64_t)j * rld];
+    } else {
+      const int e = j & 15;
+      switch (j >> 4) {
+#define RN_AT(K)                                                     \
+        case K:                                                      \
+          if constexpr (K < NSEG) {                                  \
+            double v = c##K[e];                                      \
+            asm volatile("" : "+v"(v));                              \
+            return v;                                                \
+          }                                                          \
+          break;
+        RN_SEGS(RN_AT)
+#undef RN_AT
+      }
+      return 0.0;
+    }
+  };
+
   for (int i = 0; i < N; ++i) {
     int32_t v = 0;
     if (valid) v = p.x0_ld ? p.x0[(int64_t)i * p.x0_ld + tl] : p.x0[i];
@@ -155,10 +245,9 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   int mode = valid ? (p.method == 1 ? kSsa : kDecide) : kDone;
   const bool ssa_only = p.method == 1;
 
-  auto rate = [&](int j) -> double { return crate[(int64_t)j * rld]; };
   // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
   auto prop = [&](int j, double c) -> double {
-    const RateLaw L = g.law[j];
+    const RateLaw L = law_at(g.law, j);
     const double A = (double)xc[L.ia * WG];
     const double B = (double)(xc[L.ib * WG] + L.db);
     double h = A * B;
@@ -183,9 +272,9 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   auto steps = [&]() -> uint64_t { return leaps + ssa + rej; };
   // Net change of reaction j applied k times to buffer x.
   auto apply = [&](int32_t* x, int j, int32_t k) {
-    const int e1 = g.nu_ptr[j + 1];
-    for (int e = g.nu_ptr[j]; e < e1; ++e) {
-      const int2 en = g.nu_ent[e];
+    const int e1 = cld(g.nu_ptr, j + 1);
+    for (int e = cld(g.nu_ptr, j); e < e1; ++e) {
+      const int2 en = cld2(g.nu_ent, e);
       x[en.x * WG] += k * en.y;
     }
   };
@@ -196,14 +285,23 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   }
 
   for (;;) {
-    if (!__any(mode != kDone)) break;
+    const uint64_t act = __ballot(mode != kDone);
+    if (act == 0) break;
+    const uint64_t in_ssa = __ballot(mode == kSsa);
+    // Leap-side phases run for the whole wave at once: when no lane is in an SSA
+    // burst, or when enough lanes wait for them (the rest of the time waiting
+    // lanes idle while the bursting lanes advance).
+    const uint64_t waiting = act & ~in_ssa;
+    const bool leap_turn = in_ssa == 0 ||
+                           (waiting != 0 && (float)__popcll(waiting) >=
+                                                p.theta * (float)__popcll(act));
 
     // ---------------- one exact SSA event ----------------
     if (mode == kSsa) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
         double sum = 0.0;
-        for (int j = 0; j < M; ++j) sum = sum + prop(j, rate(j));
+        each_rate([&](int j, double c) { sum = sum + prop(j, c); return true; });
         if (sum == 0.0) { finish(kStAbsorbed); break; }
         const Words w = philox10(traj, n, 0u, kStreamEvent, k0, k1);
         const double tau = -log(1.0 - u53(w.w0, w.w1)) / sum;
@@ -213,15 +311,15 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         const double r = u53(w.w2, w.w3) * sum;
         double acc = 0.0;
         int pick = -1, last = -1;
-        for (int j = 0; j < M; ++j) {
-          if (!__any(pick < 0)) break;
+        each_rate([&](int j, double c) {
           if (pick < 0) {
-            const double a = prop(j, rate(j));
+            const double a = prop(j, c);
             acc = acc + a;
             if (a > 0.0) last = j;
             if (r < acc) pick = j;
           }
-        }
+          return __any(pick < 0);
+        });
         if (pick < 0) pick = last;
         if (pick < 0) { finish(kStAbsorbed); break; }
         bool bad = false;
@@ -244,39 +342,42 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
       } while (false);
     }
 
+    if (!leap_turn) continue;
+
     // ---------------- decide: propensities, critical set, tau' ----------------
     if (mode == kDecide) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
         double sum = 0.0;
-        for (int w = 0; w < g.crit_words; ++w) {
-          uint32_t bits = 0;
-          const int jend = min(M, 32 * w + 32);
-          for (int j = 32 * w; j < jend; ++j) {
-            const double a = prop(j, rate(j));
-            sum = sum + a;
-            if (a > 0.0) {
-              bool cr = false;
-              const int e1 = g.cons_ptr[j + 1];
-              for (int e = g.cons_ptr[j]; e < e1; ++e) {
-                const int2 ce = g.cons_ent[e];
-                if ((int64_t)xc[ce.x * WG] < (int64_t)p.n_c * ce.y) cr = true;
-              }
-              if (cr) bits |= 1u << (j - 32 * w);
+        uint32_t bits = 0;
+        each_rate([&](int j, double c) {
+          const double a = prop(j, c);
+          sum = sum + a;
+          if (a > 0.0) {
+            bool cr = false;
+            const int e1 = cld(g.cons_ptr, j + 1);
+            for (int e = cld(g.cons_ptr, j); e < e1; ++e) {
+              const int2 ce = cld2(g.cons_ent, e);
+              if ((int64_t)xc[ce.x * WG] < (int64_t)p.n_c * ce.y) cr = true;
             }
+            if (cr) bits |= 1u << (j & 31);
           }
-          crit[w * WG] = (int32_t)bits;
-        }
+          if ((j & 31) == 31 || j == M - 1) {
+            crit[(j >> 5) * WG] = (int32_t)bits;
+            bits = 0;
+          }
+          return true;
+        });
         a0 = sum;
         if (sum == 0.0) { finish(kStAbsorbed); break; }
         double tp = __builtin_inf();
         for (int r = 0; r < g.n_rs; ++r) {
-          const TauSpecies ts = g.rs[r];
+          const TauSpecies ts = rs_at(g.rs, r);
           double mu = 0.0, sig = 0.0;
           for (int e = ts.begin; e < ts.end; ++e) {
-            const int2 en = g.rs_ent[e];
+            const int2 en = cld2(g.rs_ent, e);
             if (critbit(en.x)) continue;
-            const double a = prop(en.x, rate(en.x));
+            const double a = prop(en.x, rate_at(en.x));
             mu = mu + (double)en.y * a;
             sig = sig + (double)(en.y * en.y) * a;
           }
@@ -306,13 +407,16 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
           burst_left = (uint32_t)p.ssa_burst;
           break;
         }
+        uint32_t any_crit = 0;
+        for (int w = 0; w < g.crit_words; ++w) any_crit |= (uint32_t)crit[w * WG];
         double a0c = 0.0;
-        for (int w = 0; w < g.crit_words; ++w) {
-          const uint32_t bits = (uint32_t)crit[w * WG];
-          if (!__any(bits != 0u)) continue;
-          const int jend = min(M, 32 * w + 32);
-          for (int j = 32 * w; j < jend; ++j)
-            if ((bits >> (j - 32 * w)) & 1u) a0c = a0c + prop(j, rate(j));
+        if (__any(any_crit != 0u)) {
+          uint32_t cw = 0;
+          each_rate([&](int j, double c) {
+            if ((j & 31) == 0) cw = (uint32_t)crit[(j >> 5) * WG];
+            if ((cw >> (j & 31)) & 1u) a0c = a0c + prop(j, c);
+            return true;
+          });
         }
         Words ev = {0u, 0u, 0u, 0u};
         double tau_c = __builtin_inf();
@@ -331,39 +435,54 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
           xmax = max(xmax, v);
         }
         uint64_t kabs = 0;
-        for (int j = 0; j < M; j += 2) {
-          const bool two = j + 1 < M;
-          double l0 = 0.0, l1 = 0.0;
-          if (!critbit(j)) l0 = prop(j, rate(j)) * tau;
-          if (two && !critbit(j + 1)) l1 = prop(j + 1, rate(j + 1)) * tau;
+        // Poisson firings, two reactions per Philox block of the first-uniform
+        // stream: the even reaction's rate is held until its odd partner arrives.
+        uint32_t cw = 0;
+        double l_even = 0.0;
+        auto draw_pair = [&](int je, double le, double lo, bool two) {
           Words w = {0u, 0u, 0u, 0u};
-          if ((l0 > 0.0 && l0 < 10.0) || (l1 > 0.0 && l1 < 10.0))
-            w = philox10(traj, n, (uint32_t)(j >> 1), kStreamFirst, k0, k1);
-          const uint32_t d0 = poisson(l0, w.w0, w.w1, traj, n, (uint32_t)j, k0, k1);
-          const uint32_t d1 = poisson(l1, w.w2, w.w3, traj, n, (uint32_t)(j + 1), k0, k1);
-          if (__any(d0 != 0u)) apply(xn, j, (int32_t)d0);
-          if (two && __any(d1 != 0u)) apply(xn, j + 1, (int32_t)d1);
-          kabs += (uint64_t)d0 * g.nu_abs[j];
-          if (two) kabs += (uint64_t)d1 * g.nu_abs[j + 1];
-        }
+          if ((le > 0.0 && le < 10.0) || (lo > 0.0 && lo < 10.0))
+            w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
+          const uint32_t d0 = poisson(le, w.w0, w.w1, traj, n, (uint32_t)je, k0, k1, g.log_fact);
+          const uint32_t d1 = poisson(lo, w.w2, w.w3, traj, n, (uint32_t)(je + 1), k0, k1, g.log_fact);
+          if (__any(d0 != 0u)) apply(xn, je, (int32_t)d0);
+          kabs += (uint64_t)d0 * (uint32_t)cld(g.nu_abs, je);
+          if (two) {
+            if (__any(d1 != 0u)) apply(xn, je + 1, (int32_t)d1);
+            kabs += (uint64_t)d1 * (uint32_t)cld(g.nu_abs, je + 1);
+          }
+        };
+        each_rate([&](int j, double c) {
+          if ((j & 31) == 0) cw = (uint32_t)crit[(j >> 5) * WG];
+          const double l = ((cw >> (j & 31)) & 1u) ? 0.0 : prop(j, c) * tau;
+          if ((j & 1) == 0) {
+            l_even = l;
+            if (j == M - 1) draw_pair(j, l_even, 0.0, false);
+          } else {
+            draw_pair(j - 1, l_even, l, true);
+          }
+          return true;
+        });
         int jc = -1;
         if (fire) {
           const double r = u53(ev.w2, ev.w3) * a0c;
           double acc = 0.0;
           int last = -1;
-          for (int j = 0; j < M; ++j) {
-            if (!__any(jc < 0)) break;
-            if (jc < 0 && critbit(j)) {
-              const double a = prop(j, rate(j));
+          uint32_t cw2 = 0;
+          each_rate([&](int j, double c) {
+            if ((j & 31) == 0) cw2 = (uint32_t)crit[(j >> 5) * WG];
+            if (jc < 0 && ((cw2 >> (j & 31)) & 1u)) {
+              const double a = prop(j, c);
               acc = acc + a;
               if (a > 0.0) last = j;
               if (r < acc) jc = j;
             }
-          }
+            return __any(jc < 0);
+          });
           if (jc < 0) jc = last;
           if (jc < 0) { finish(kStAbsorbed); break; }
           apply(xn, jc, 1);
-          kabs += g.nu_abs[jc];
+          kabs += (uint32_t)cld(g.nu_abs, jc);
         }
 
         bool neg = false, big = false;
@@ -374,20 +493,20 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
           // exact 64-bit evaluation, species by species, redrawing each k_j
           for (int i = 0; i < N; ++i) {
             int64_t acc = xc[i * WG];
-            for (int e = g.col_ptr[i]; e < g.col_ptr[i + 1]; ++e) {
-              const int2 en = g.col_ent[e];
+            for (int e = cld(g.col_ptr, i); e < cld(g.col_ptr, i + 1); ++e) {
+              const int2 en = cld2(g.col_ent, e);
               const int j = en.x;
               int64_t kj;
               if (critbit(j)) {
                 kj = (fire && j == jc) ? 1 : 0;
               } else {
-                const double lam = prop(j, rate(j)) * tau;
+                const double lam = prop(j, rate_at(j)) * tau;
                 Words w = {0u, 0u, 0u, 0u};
                 if (lam > 0.0 && lam < 10.0)
                   w = philox10(traj, n, (uint32_t)(j >> 1), kStreamFirst, k0, k1);
                 const uint32_t hi = (j & 1) ? w.w2 : w.w0;
                 const uint32_t lo = (j & 1) ? w.w3 : w.w1;
-                kj = poisson(lam, hi, lo, traj, n, (uint32_t)j, k0, k1);
+                kj = poisson(lam, hi, lo, traj, n, (uint32_t)j, k0, k1, g.log_fact);
               }
               acc += kj * (int64_t)en.y;
             }
@@ -425,30 +544,38 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   }
 }
 
+template <int WG, int NSEG>
+hipError_t launch_one(const SweepParams& p, size_t lds, hipStream_t stream, int64_t blocks) {
+  hipError_t err = hipFuncSetAttribute((const void*)sweep_kernel<WG, NSEG>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((sweep_kernel<WG, NSEG>), dim3((unsigned)blocks), dim3(WG), lds, stream, p);
+  return hipGetLastError();
+}
+
+template <int WG>
+hipError_t launch_wg(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream,
+                     int64_t blocks) {
+  switch (cfg.rate_segs) {
+#define RN_CASE(K) \
+    case K + 1: return launch_one<WG, K + 1>(p, cfg.lds_bytes, stream, blocks);
+    RN_SEGS(RN_CASE)
+#undef RN_CASE
+    case 0: return launch_one<WG, 0>(p, cfg.lds_bytes, stream, blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_sweep(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream) {
   const int64_t blocks = (p.n_traj + cfg.wg - 1) / cfg.wg;
   if (blocks <= 0) return hipSuccess;
-  hipError_t err = hipSuccess;
   switch (cfg.wg) {
-    case 64:
-      err = hipFuncSetAttribute((const void*)sweep_kernel<64>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
-      if (err != hipSuccess) return err;
-      hipLaunchKernelGGL(sweep_kernel<64>, dim3((unsigned)blocks), dim3(64), cfg.lds_bytes, stream, p);
-      break;
-    case 256:
-      err = hipFuncSetAttribute((const void*)sweep_kernel<256>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
-      if (err != hipSuccess) return err;
-      hipLaunchKernelGGL(sweep_kernel<256>, dim3((unsigned)blocks), dim3(256), cfg.lds_bytes, stream,
-                         p);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 64: return launch_wg<64>(p, cfg, stream, blocks);
+    case 256: return launch_wg<256>(p, cfg, stream, blocks);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace rn

@@ -36,6 +36,10 @@ class _Params(C.Structure):
                 ("max_steps", C.c_uint64), ("method", C.c_int32)]
 
 
+class _OdeParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
+
+
 OPS_FIELDS = ["leaps", "ssa_events", "rejections", "prop_evals", "crit_tests", "tau_terms",
               "tau_species", "philox_blocks", "inv_draws", "inv_iters", "ptrs_draws",
               "ptrs_iters", "ptrs_log_tests", "exp_draws", "select_terms", "update_terms"]
@@ -66,6 +70,10 @@ def lib():
                               C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_run.restype = C.c_int
+        L.orc_ode_run.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                  C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
+                                  C.c_void_p, C.c_void_p]
+        L.orc_ode_run.restype = C.c_int
         _lib = L
     return _lib
 
@@ -159,3 +167,48 @@ def run(net, rates, x0, times, *, seed, eps=0.03, n_c=10, ssa_factor=10.0, ssa_b
     if counters:
         ops = {f: sum(getattr(o, f) for o in ops_list) for f in OPS_FIELDS}
     return out, stats, ops
+
+
+def ode_run(net, rates, x0, times, *, rtol=1e-6, atol=1e-6, max_steps=10**7, traj_range=None,
+            threads=1):
+    """Reaction-rate equations by Dormand-Prince 5(4) for trajectories ``traj_range``.
+
+    Returns ``(out [S][N][T] float64, stats [T][4] uint64)`` with stats = (accepted
+    steps, rejected steps, 0, status)."""
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    M, T = rates.shape
+    a, b = traj_range if traj_range is not None else (0, T)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    S, N = len(times), net.n_species
+    n = b - a
+    out = np.zeros((S, N, n), dtype=np.float64)
+    stats = np.zeros((n, 4), dtype=np.uint64)
+    desc, keep = _desc(net)
+    par = _OdeParams(float(rtol), float(atol), int(max_steps))
+    L = lib()
+    nth = max(1, min(int(threads), n)) if n > 0 else 1
+    bounds = np.linspace(0, n, nth + 1).astype(np.int64)
+
+    def work(ci):
+        lo, hi = int(bounds[ci]), int(bounds[ci + 1])
+        if hi <= lo:
+            return 0
+        rp = rates.ctypes.data + 8 * (a + lo)
+        if x0.ndim == 2:
+            xp, xld = x0.ctypes.data + 4 * (a + lo), T
+        else:
+            xp, xld = x0.ctypes.data, 0
+        return L.orc_ode_run(C.byref(desc), rp, T, xp, xld, times.ctypes.data, S, hi - lo,
+                             out.ctypes.data + 8 * lo, n, stats.ctypes.data + 32 * lo, C.byref(par))
+
+    if nth == 1:
+        rcs = [work(0)]
+    else:
+        with ThreadPoolExecutor(nth) as ex:
+            rcs = list(ex.map(work, range(nth)))
+    for rc in rcs:
+        if rc != 0:
+            raise RuntimeError(f"oracle error {rc}")
+    del keep
+    return out, stats

@@ -12,10 +12,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
-    src = os.path.join(HERE, "oracle.c")
+    srcs = [os.path.join(HERE, "oracle.c"), os.path.join(HERE, "ode.c")]
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+           "-Wall", "-Wextra", "-o", tmp, *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

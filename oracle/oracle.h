@@ -92,6 +92,26 @@ int orc_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
             int64_t traj_first, int64_t n_traj, int32_t *out, int64_t out_ld,
             uint64_t *stats, const orc_params *par, orc_ops *ops);
 
+/*
+ * Deterministic counterpart (paper, Methods section: when every species is
+ * abundant, X(t) is well approximated by the reaction-rate equations, and the
+ * thermodynamic limit makes the stochastic and mean-field models agree):
+ *   dy/dt = sum_j nu_j c_j h_j(y),  h_j = 1, y_a, y_a*y_b, or y_a^2/2 (homodimer),
+ * integrated with the Dormand-Prince 5(4) embedded Runge-Kutta pair and an
+ * error-per-step controller; steps are clipped to the sample times.
+ *   out   : out[(s*N + i)*out_ld + t] (double)
+ *   stats : stats[t*4 + {0: accepted steps, 1: rejected steps, 2: 0, 3: status}]
+ */
+typedef struct {
+  double rtol, atol;
+  uint64_t max_steps;  /* accepted + rejected steps per trajectory */
+} orc_ode_params;
+
+int orc_ode_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
+                const int32_t *x0, int64_t x0_ld, const double *times, int32_t n_times,
+                int64_t n_traj, double *out, int64_t out_ld, uint64_t *stats,
+                const orc_ode_params *par);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,19 +28,23 @@ METRIC = "trajectory-steps/sec at 65,536 sims (1 GPU); p50/p99 sweep-job latency
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic cost of each primitive the oracle counts, in full-rate VALU lane
-# operations on gfx950 (quarter-rate instructions count 4).
+# operations on gfx950: the VALU instructions the compiler emits for that
+# primitive in isolation (quarter-rate ones -- 32x32->64 multiplies, f64
+# reciprocal/sqrt seeds -- weighted 4).  Measured from the ISA of one-primitive
+# kernels: Philox4x32-10 block 140, f64 exp 45, f64 log 117, f64 divide 15,
+# sqrt 31, 53-bit uniform 14.
 OP_COST = {
-    "prop_evals": 6,        # 2 int->f64 converts, 2-3 f64 multiplies, 1 add to a0
+    "prop_evals": 8,        # 2 int->f64 converts, 3 f64 multiplies, 1 add, 2 address adds
     "crit_tests": 2,        # one integer product and compare
-    "tau_terms": 5,         # convert nu, 2 multiplies, 2 adds
-    "tau_species": 30,      # g_i, b_i, 2 f64 divides (~10 each), 2 mins
-    "philox_blocks": 100,   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 xor3)
-    "inv_draws": 32,        # u53 conversion (6) + f64 exp (~24) + compare
-    "inv_iters": 14,        # f64 divide 1/k (~10) + 2 multiplies + add + compare
-    "ptrs_draws": 60,       # sqrt, log, 2 divides of the set-up
-    "ptrs_iters": 30,       # 2 u53, divide, floor, compares
-    "ptrs_log_tests": 90,   # 2 logs and an lgamma
-    "exp_draws": 36,        # f64 log (~24) + divide (~10) + u53
+    "tau_terms": 6,         # critical-bit test, convert, 2 multiplies, 2 adds
+    "tau_species": 40,      # g_i, b_i, 2 f64 divides, 2 mins
+    "philox_blocks": 140,   # 10 rounds, 20 quarter-rate multiplies
+    "inv_draws": 60,        # 53-bit uniform + f64 exp + compare
+    "inv_iters": 20,        # f64 divide 1/k + 2 multiplies + add + compare
+    "ptrs_draws": 185,      # sqrt, log, 2 divides of the set-up
+    "ptrs_iters": 60,       # 2 uniforms, divide, floor, compares
+    "ptrs_log_tests": 260,  # 2 logs, a divide, the log-factorial
+    "exp_draws": 146,       # 53-bit uniform + f64 log + divide
     "select_terms": 2,      # running sum and compare
     "update_terms": 2,      # integer multiply-add and range check
 }

@@ -27,7 +27,7 @@ extern "C" {
 #endif
 
 #define RN_OK 0
-#define RN_E_INVALID_ARG (-1)     /* null pointer, bad size, bad times, bad option      */
+#define RN_E_INVALID_ARG (-1)     /* null pointer, bad size, bad option                 */
 #define RN_E_INVALID_NETWORK (-2) /* species index out of range, coefficient <= 0 ...   */
 #define RN_E_UNSUPPORTED (-3)     /* a reaction with three or more reactant molecules   */
 #define RN_E_NOMEM (-4)           /* host or device allocation failed                   */
@@ -101,12 +101,14 @@ int rn_sample_times(double t_end, int32_t n_points, double *out);
  *               trajectory-minor), rates_ld >= n_traj; finite and >= 0.
  *  x0           device, int32: x0[i] (x0_ld == 0, broadcast to every
  *               trajectory) or x0[i * x0_ld + t] (x0_ld >= n_traj); >= 0.
- *  times        device, double[n_times], finite, >= 0, strictly increasing.
+ *  times        device, double[n_times]; must be finite, >= 0 and strictly
+ *               increasing (device memory is not inspected on the host; the
+ *               Python binding checks it before upload).
  *  out          device, int32, out[(s * n_species + i) * out_ld + t] receives
  *               X_i(times[s]) of trajectory t; out_ld >= n_traj.
  *  stats        device, uint64[n_traj][4]: accepted leaps, SSA events,
  *               rejected leaps, status bits (RN_ST_*).
- *  eps          leap-condition tolerance (0 < eps < 1); n_c critical threshold
+ *  eps          leap-condition tolerance (finite, > 0); n_c critical threshold
  *               (0 <= n_c <= 2^20); ssa_factor: leap only when
  *               tau' >= ssa_factor / a0 (>= 0); ssa_burst: exact events per
  *               burst (>= 1); max_steps: per-trajectory cap on leaps + SSA
@@ -139,13 +141,85 @@ typedef struct {
   uint64_t max_steps;
   int32_t method;
   int32_t precision;
+  /* 0 (off), or >= 10: a leap's firing count of a non-critical reaction whose
+   * mean lam reaches this value is drawn from the Chemical Langevin increment
+   * round(lam + sqrt(lam) z), z standard normal (Box-Muller on the reaction's
+   * first PTRS block), floored at 0 -- the CLE-based approximation of the
+   * paper's Methods section, in place of the Poisson draw. */
+  double cle_threshold;
 } rn_sweep_args;
 
 /* Defaults: eps 0.03, n_c 10, ssa_factor 10, ssa_burst 100, max_steps 1e8,
- * tau-leaping, FP64 (CGP 2006's recommended switch constants). */
+ * tau-leaping, FP64, CLE off (CGP 2006's recommended switch constants). */
 void rn_sweep_args_init(rn_sweep_args *args);
 
 int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream);
+
+/*
+ * Deterministic sweep: the reaction-rate equations that abundant species follow
+ * (paper, Methods section: mean-field ODEs, which agree with the stochastic
+ * model in the thermodynamic limit),
+ *   dy/dt = sum_j nu_j c_j h_j(y),  h_j = 1, y_a, y_a*y_b, or y_a^2/2 (homodimer),
+ * one trajectory per parameterization, from y(0) = x0, integrated by the
+ * Dormand-Prince 5(4) pair with error control (rms over species of
+ * e_i / (atol + rtol * max(|y_i|, |y_i'|)) <= 1) and steps ending exactly on
+ * the sample times.
+ *
+ *  rates, x0, times  as for rn_sweep (device; rates_ld, x0_ld likewise).
+ *  out        device, double, out[(s * n_species + i) * out_ld + t] = y_i(times[s]).
+ *  stats      device, uint64[n_traj][4]: accepted steps, rejected steps, 0,
+ *             status (RN_ST_MAXSTEPS when accepted + rejected reach max_steps;
+ *             later samples repeat the last state).
+ *  work       device scratch of 10 * n_species rows of work_ld doubles
+ *             (work_ld >= n_traj; rn_ode_work_doubles gives the total for
+ *             work_ld = n_traj), caller-owned; its contents on entry are ignored.
+ *  rtol, atol finite, > 0; max_steps >= 1.
+ * Asynchronous on `hip_stream`; allocates nothing.  Errors: RN_E_INVALID_ARG,
+ * RN_E_DEVICE.
+ */
+typedef struct {
+  int64_t n_traj;
+  const double *rates;
+  int64_t rates_ld;
+  const int32_t *x0;
+  int64_t x0_ld;
+  const double *times;
+  int32_t n_times;
+  double *out;
+  int64_t out_ld;
+  uint64_t *stats;
+  double *work;
+  int64_t work_ld;
+  double rtol, atol;
+  uint64_t max_steps;
+} rn_ode_args;
+
+/* Defaults: rtol 1e-6, atol 1e-6, max_steps 1e7. */
+void rn_ode_args_init(rn_ode_args *args);
+
+/* Doubles of workspace rn_ode_sweep needs for n_traj trajectories with
+ * work_ld = n_traj (-1 for a null handle or a negative n_traj). */
+int64_t rn_ode_work_doubles(const rn_network *net, int64_t n_traj);
+
+int rn_ode_sweep(const rn_network *net, const rn_ode_args *args, void *hip_stream);
+
+/*
+ * Ensemble moments of a sweep's samples, the summary that parameter sweeps,
+ * sensitivity analysis and parameter estimation consume (paper, Aims and
+ * motivation section).  For every sample s < n_times and species i < n_species,
+ * over trajectories t < n_traj of out[(s * n_species + i) * out_ld + t]:
+ *   sum_x[s * n_species + i]              = sum_t x         (int64, exact)
+ *   sum_x2[2 * (s * n_species + i) + 0/1] = sum_t x^2       (unsigned 128-bit:
+ *                                           low word, high word; exact)
+ * Mean and unbiased variance follow as m = S1/T and (S2 - S1^2/T)/(T - 1).
+ * `out` is the int32 sample array of rn_sweep (device); sum_x and sum_x2 are
+ * caller-owned device arrays of n_times*n_species int64 and 2*n_times*n_species
+ * uint64.  Asynchronous on `hip_stream`; allocates nothing.  Errors:
+ * RN_E_INVALID_ARG (null pointer, non-positive size, out_ld < n_traj,
+ * n_times * n_species >= 2^31), RN_E_DEVICE.
+ */
+int rn_moments(const int32_t *out, int64_t out_ld, int32_t n_times, int32_t n_species,
+               int64_t n_traj, int64_t *sum_x, uint64_t *sum_x2, void *hip_stream);
 
 /* Message for an RN_* code (static storage). */
 const char *rn_strerror(int code);

@@ -33,7 +33,7 @@ class _NetDesc(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("eps", C.c_double), ("n_c", C.c_int32),
                 ("ssa_factor", C.c_double), ("ssa_burst", C.c_int32),
-                ("max_steps", C.c_uint64), ("method", C.c_int32)]
+                ("max_steps", C.c_uint64), ("method", C.c_int32), ("cle_threshold", C.c_double)]
 
 
 class _OdeParams(C.Structure):
@@ -66,6 +66,9 @@ def lib():
         L.orc_poisson_many.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_int32, C.c_int64,
                                        C.c_void_p]
         L.orc_poisson_many.restype = None
+        L.orc_cle_many.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_int32, C.c_int64,
+                                   C.c_void_p]
+        L.orc_cle_many.restype = None
         L.orc_run.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_void_p]
@@ -109,8 +112,15 @@ def _desc(net):
     return d, arrs
 
 
+def cle_many(lam, seed, n, j=0, n0=0):
+    out = np.zeros(int(n), dtype=np.int64)
+    lib().orc_cle_many(float(lam), int(seed), int(n0), int(j), int(n), out.ctypes.data)
+    return out
+
+
 def run(net, rates, x0, times, *, seed, eps=0.03, n_c=10, ssa_factor=10.0, ssa_burst=100,
-        max_steps=10**8, method="tauleap", traj_range=None, threads=1, counters=False):
+        max_steps=10**8, method="tauleap", traj_range=None, threads=1, counters=False,
+        cle_threshold=0.0):
     """Simulate trajectories ``traj_range = (a, b)`` (default: all columns of ``rates``).
 
     Returns ``(out, stats, ops)``: ``out`` int32 ``[S][N][b-a]``, ``stats`` uint64
@@ -132,7 +142,7 @@ def run(net, rates, x0, times, *, seed, eps=0.03, n_c=10, ssa_factor=10.0, ssa_b
     stats = np.zeros((n, 4), dtype=np.uint64)
     desc, keep = _desc(net)
     par = _Params(int(seed), float(eps), int(n_c), float(ssa_factor), int(ssa_burst),
-                  int(max_steps), 1 if method == "ssa" else 0)
+                  int(max_steps), 1 if method == "ssa" else 0, float(cle_threshold))
     L = lib()
     chunks = []
     nth = max(1, min(int(threads), n)) if n > 0 else 1

@@ -126,6 +126,26 @@ int64_t orc_poisson(double lam, uint64_t seed, uint32_t traj, uint32_t n, int32_
   }
 }
 
+/* Chemical Langevin increment (the CLE-based approximation of the paper's
+ * Methods section, applied to one reaction's firings over a leap): the Poisson
+ * count is replaced by a Gaussian of the same mean and variance, rounded to the
+ * nearest integer and floored at zero.  z = sqrt(-2 ln(1-u1)) cos(2 pi u2)
+ * (Box-Muller), (u1, u2) from the reaction's first PTRS block. */
+int64_t orc_cle_count(double lam, uint64_t seed, uint32_t traj, uint32_t n, int32_t j) {
+  uint32_t w[4];
+  block(seed, traj, n, (uint32_t)j, STREAM_PTRS, w);
+  double u1 = orc_u53(w[0], w[1]);
+  double u2 = orc_u53(w[2], w[3]);
+  double z = sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+  double kf = floor(lam + sqrt(lam) * z + 0.5);
+  if (kf < 0.0) kf = 0.0;
+  return (int64_t)(kf < K_CLAMP ? kf : K_CLAMP);
+}
+
+void orc_cle_many(double lam, uint64_t seed, uint32_t n0, int32_t j, int64_t n, int64_t *out) {
+  for (int64_t t = 0; t < n; ++t) out[t] = orc_cle_count(lam, seed, (uint32_t)t, n0, j);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Network preprocessing                                                     */
 /* ------------------------------------------------------------------------- */
@@ -393,7 +413,10 @@ static void simulate(traj_state *T) {
           last_pair = j >> 1;
           if (T->ops) T->ops->philox_blocks++;
         }
-        T->k[j] = orc_poisson(lam, P->seed, T->traj, T->n, j, T->ops);
+        if (P->cle_threshold > 0.0 && lam >= P->cle_threshold)
+          T->k[j] = orc_cle_count(lam, P->seed, T->traj, T->n, j);
+        else
+          T->k[j] = orc_poisson(lam, P->seed, T->traj, T->n, j, T->ops);
       }
       if (fire) {
         int jc = pick_reaction(T, orc_u53(ev[2], ev[3]) * a0c, T->crit);
@@ -445,6 +468,7 @@ int orc_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
     return ORC_E_ARG;
   if (par->ssa_burst < 1 || par->max_steps < 1 || !(par->eps > 0.0) || !(par->ssa_factor >= 0.0))
     return ORC_E_ARG;
+  if (!(par->cle_threshold == 0.0 || par->cle_threshold >= 10.0)) return ORC_E_ARG;
   for (int s = 0; s < n_times; ++s) {
     if (!(times[s] >= 0.0) || !isfinite(times[s])) return ORC_E_ARG;
     if (s > 0 && !(times[s] > times[s - 1])) return ORC_E_ARG;

@@ -38,6 +38,7 @@ typedef struct {
   int32_t ssa_burst;   /* exact events run when the switch trips                    */
   uint64_t max_steps;  /* per trajectory: leaps + ssa events + rejections           */
   int32_t method;      /* 0 = tau-leaping, 1 = exact SSA only                        */
+  double cle_threshold; /* > 0: leap firings with mean >= this are Gaussian (CLE)    */
 } orc_params;
 
 /* Counts of primitive operations, summed over the trajectories of one call. */
@@ -62,6 +63,11 @@ double orc_u53(uint32_t hi, uint32_t lo);
 /* One Poisson(lam) variate for reaction j of attempt n of trajectory traj. */
 int64_t orc_poisson(double lam, uint64_t seed, uint32_t traj, uint32_t n, int32_t j,
                     orc_ops *ops);
+
+/* Chemical-Langevin firing count for mean lam (>= 10): round(lam + sqrt(lam) z),
+ * z standard normal by Box-Muller, floored at 0 and clamped at 2^31. */
+int64_t orc_cle_count(double lam, uint64_t seed, uint32_t traj, uint32_t n, int32_t j);
+void orc_cle_many(double lam, uint64_t seed, uint32_t n0, int32_t j, int64_t n, int64_t *out);
 
 /* n variates for trajectory ids 0..n-1 (test helper). */
 void orc_poisson_many(double lam, uint64_t seed, uint32_t n0, int32_t j, int64_t n, int64_t *out);

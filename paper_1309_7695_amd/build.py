@@ -22,7 +22,8 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
 
 
 def sources():
-    return [os.path.join(CSRC, "rn_host.cpp"), os.path.join(CSRC, "rn_sweep.hip")]
+    return [os.path.join(CSRC, "rn_host.cpp"), os.path.join(CSRC, "rn_sweep.hip"),
+            os.path.join(CSRC, "rn_moments.hip"), os.path.join(CSRC, "rn_ode.hip")]
 
 
 def build(verbose=False, extra=()):

@@ -60,8 +60,15 @@ struct HostTables {
   int32_t crit_words = 0;
 };
 
+// Number of reactions the kernels see: networks held in register rate vectors
+// are padded with null reactions to a multiple of 16.
+int32_t padded_reactions(int32_t M) {
+  return M <= 16 * rn::kMaxRateSegs ? (M + 15) / 16 * 16 : M;
+}
+
 int build_tables(const rn_network_desc* d, HostTables& T) {
   const int32_t N = d->n_species, M = d->n_reactions;
+  const int32_t Mp = padded_reactions(M);
   if (!d->react_ptr || !d->prod_ptr) return RN_E_INVALID_ARG;
   if (d->react_ptr[0] != 0 || d->prod_ptr[0] != 0) return RN_E_INVALID_ARG;
   for (int32_t j = 0; j < M; ++j)
@@ -73,8 +80,8 @@ int build_tables(const rn_network_desc* d, HostTables& T) {
 
   std::vector<int32_t> hor(N, 0), dimer(N, 0);
   std::vector<std::vector<std::pair<int32_t, int32_t>>> nu(M);  // per reaction (species, nu)
-  T.law.resize(M);
-  T.nu_abs.resize(M);
+  T.law.assign(Mp, rn::RateLaw{N, N, 0, 0});
+  T.nu_abs.assign(Mp, 0u);
   for (int32_t j = 0; j < M; ++j) {
     std::map<int32_t, int64_t> r, net;
     int64_t order = 0;
@@ -132,6 +139,10 @@ int build_tables(const rn_network_desc* d, HostTables& T) {
     T.nu_ptr.push_back((int32_t)T.nu_ent.size());
     T.cons_ptr.push_back((int32_t)T.cons_ent.size());
   }
+  for (int32_t j = M; j < Mp; ++j) {  // null reactions
+    T.nu_ptr.push_back((int32_t)T.nu_ent.size());
+    T.cons_ptr.push_back((int32_t)T.cons_ent.size());
+  }
   T.col_ptr.assign(1, 0);
   for (int32_t i = 0; i < N; ++i) {
     for (auto& e : col[i]) T.col_ent.push_back(e);
@@ -147,7 +158,7 @@ int build_tables(const rn_network_desc* d, HostTables& T) {
     ts.end = (int32_t)T.rs_ent.size();
     T.rs.push_back(ts);
   }
-  T.crit_words = (M + 31) / 32;
+  T.crit_words = (Mp + 31) / 32;
   T.log_fact.resize(rn::kLogFactTable);
   for (int k = 0; k < rn::kLogFactTable; ++k) T.log_fact[k] = std::lgamma((double)k + 1.0);
   return RN_OK;
@@ -243,7 +254,8 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
   unsigned char* b = (unsigned char*)net->dbuf;
   rn::DevNet& D = net->dev;
   D.N = net->N;
-  D.M = net->M;
+  D.M = padded_reactions(net->M);
+  D.M_real = net->M;
   D.n_rs = (int32_t)T.rs.size();
   D.crit_words = T.crit_words;
   D.law = (const rn::RateLaw*)(b + o_law);
@@ -278,6 +290,8 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   if (a->ssa_burst < 1 || a->max_steps < 1) return RN_E_INVALID_ARG;
   if (a->method != RN_METHOD_TAULEAP && a->method != RN_METHOD_SSA) return RN_E_INVALID_ARG;
   if (a->precision != RN_FP64) return RN_E_INVALID_ARG;
+  if (!(a->cle_threshold == 0.0 || (a->cle_threshold >= 10.0 && a->cle_threshold <= 1e300)))
+    return RN_E_INVALID_ARG;
   if (a->n_traj == 0) return RN_OK;
   if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats) return RN_E_INVALID_ARG;
   if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj) return RN_E_INVALID_ARG;
@@ -293,9 +307,10 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return device_error(e);
 
-  const size_t per_lane = rn::lds_words_per_lane(net->N, net->M) * sizeof(int32_t);
+  const size_t per_lane =
+      rn::lds_words_per_lane(net->N, padded_reactions(net->M)) * sizeof(int32_t);
   rn::LaunchCfg cfg{};
-  cfg.rate_segs = net->M <= 16 * rn::kMaxRateSegs ? (net->M + 15) / 16 : 0;
+  cfg.rate_segs = net->M <= 16 * rn::kMaxRateSegs ? padded_reactions(net->M) / 16 : 0;
   // 256 lanes per workgroup (one wave per SIMD of a CU) when the sweep fills the
   // chip; otherwise single-wave workgroups spread over more CUs.
   if (a->n_traj >= (int64_t)256 * n_cu && per_lane * 256 <= (size_t)max_lds) cfg.wg = 256;
@@ -324,8 +339,71 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   p.ssa_burst = a->ssa_burst;
   p.max_steps = a->max_steps;
   p.method = a->method;
+  p.cle_threshold = a->cle_threshold;
   p.theta = sched_theta();
   e = rn::launch_sweep(p, cfg, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return device_error(e);
+  return RN_OK;
+}
+
+void rn_ode_args_init(rn_ode_args* a) {
+  if (!a) return;
+  std::memset(a, 0, sizeof(*a));
+  a->rtol = 1e-6;
+  a->atol = 1e-6;
+  a->max_steps = 10000000ull;
+}
+
+int64_t rn_ode_work_doubles(const rn_network* net, int64_t n_traj) {
+  if (!net || n_traj < 0) return -1;
+  return (int64_t)rn::kOdeSlots * net->N * n_traj;
+}
+
+int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) {
+  if (!net || !a) return RN_E_INVALID_ARG;
+  if (a->n_traj < 0 || a->n_times < 1) return RN_E_INVALID_ARG;
+  if (!(a->rtol > 0.0) || !std::isfinite(a->rtol) || !(a->atol > 0.0) || !std::isfinite(a->atol))
+    return RN_E_INVALID_ARG;
+  if (a->max_steps < 1) return RN_E_INVALID_ARG;
+  if (a->n_traj == 0) return RN_OK;
+  if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats || !a->work) return RN_E_INVALID_ARG;
+  if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj || a->work_ld < a->n_traj)
+    return RN_E_INVALID_ARG;
+  if (a->x0_ld != 0 && a->x0_ld < a->n_traj) return RN_E_INVALID_ARG;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e);
+  if (dev != net->device) return RN_E_INVALID_ARG;
+  rn::OdeParams p{};
+  p.net = net->dev;
+  p.rates = a->rates;
+  p.rates_ld = a->rates_ld;
+  p.x0 = a->x0;
+  p.x0_ld = a->x0_ld;
+  p.times = a->times;
+  p.n_times = a->n_times;
+  p.out = a->out;
+  p.out_ld = a->out_ld;
+  p.stats = a->stats;
+  p.work = a->work;
+  p.work_ld = a->work_ld;
+  p.n_traj = a->n_traj;
+  p.rtol = a->rtol;
+  p.atol = a->atol;
+  p.max_steps = a->max_steps;
+  e = rn::launch_ode(p, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return device_error(e);
+  return RN_OK;
+}
+
+int rn_moments(const int32_t* out, int64_t out_ld, int32_t n_times, int32_t n_species,
+               int64_t n_traj, int64_t* sum_x, uint64_t* sum_x2, void* hip_stream) {
+  if (!out || !sum_x || !sum_x2) return RN_E_INVALID_ARG;
+  if (n_times < 1 || n_species < 1 || n_traj < 1 || out_ld < n_traj) return RN_E_INVALID_ARG;
+  const int64_t rows = (int64_t)n_times * n_species;
+  if (rows >= ((int64_t)1 << 31)) return RN_E_INVALID_ARG;
+  const hipError_t e =
+      rn::launch_moments(out, out_ld, rows, n_traj, sum_x, sum_x2, (hipStream_t)hip_stream);
   if (e != hipSuccess) return device_error(e);
   return RN_OK;
 }

@@ -26,7 +26,9 @@ struct TauSpecies {
 };
 
 struct DevNet {
-  int32_t N, M, n_rs, crit_words;
+  // M counts the null reactions (zero rate, no stoichiometry) that pad the
+  // network to a whole number of 16-reaction rate vectors; M_real does not.
+  int32_t N, M, M_real, n_rs, crit_words;
   const RateLaw* law;        // [M]
   const int32_t* nu_ptr;     // [M+1] reaction-major net changes
   const int2* nu_ent;        // {species, nu_ij}, nu_ij != 0
@@ -62,10 +64,32 @@ struct SweepParams {
   int32_t ssa_burst;
   uint64_t max_steps;
   int32_t method;
+  double cle_threshold;  // 0: off
   // Leap-side phases run when at least this fraction of the wave's active lanes
   // waits for them (or no lane is in an SSA burst).  Scheduling only: results do
   // not depend on it.
   float theta;
+};
+
+// Reaction-rate-equation sweep (Dormand-Prince 5(4) per lane).
+constexpr int kOdeSlots = 10;  // state vectors per lane in the workspace
+
+struct OdeParams {
+  DevNet net;
+  const double* rates;
+  int64_t rates_ld;
+  const int32_t* x0;
+  int64_t x0_ld;
+  const double* times;
+  int32_t n_times;
+  double* out;
+  int64_t out_ld;
+  uint64_t* stats;
+  double* work;
+  int64_t work_ld;
+  int64_t n_traj;
+  double rtol, atol;
+  uint64_t max_steps;
 };
 
 // Launch configuration chosen by the host.
@@ -84,5 +108,8 @@ inline size_t lds_words_per_lane(int N, int M) {
 }
 
 hipError_t launch_sweep(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
+hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
+                          int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream);
 
 }  // namespace rn

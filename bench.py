@@ -27,6 +27,32 @@ METRIC = "trajectory-steps/sec at 65,536 sims (1 GPU); p50/p99 sweep-job latency
 # rate on CDNA4: 78.6 TFLOP/s counts an FMA as two flops).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_kernel_synthetic_50x100_fp64_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 sweep kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record (each counter scaled by what it
+    reads for a copy of known size), or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_1309_7695_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["kernel_sources_sha256"] else None
+
+
+def rate_segments(m):
+    """Rate-register segments of 16 the library picks for m reactions."""
+    return (m + 15) // 16 if m <= 128 else 0
+
 # Algorithmic cost of each primitive the oracle counts, in full-rate VALU lane
 # operations on gfx950: the VALU instructions the compiler emits for that
 # primitive in isolation (quarter-rate ones -- 32x32->64 multiplies, f64
@@ -59,6 +85,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2048,
                     help="trajectories of the workload the oracle runs for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
     return ap.parse_args()
 
 
@@ -85,15 +113,17 @@ def main():
     times = torch.from_numpy(w.times).to(dev)
     out = torch.empty((S, N, T), dtype=torch.int32, device=dev)
     stats = torch.empty((T, 4), dtype=torch.int64, device=dev)
-    kw = dict(seed=w.seed, eps=w.eps, n_c=w.n_c)
+    kw = dict(seed=w.seed, eps=w.eps, n_c=w.n_c, precision=args.precision)
     print(f"[bench] workload {w.name}: T={T} N={N} M={M} S={S}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         rn.sweep(net, rates, x0, times, out, stats, **kw)
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    st = stats.cpu().numpy().view(np.uint64)
-    steps_per_sweep = int(st[:, 0].sum() + st[:, 1].sum())
+    warm_steps = None
+    if args.warmup > 0:
+        st = stats.cpu().numpy().view(np.uint64)
+        warm_steps = int(st[:, 0].sum() + st[:, 1].sum())
 
     stream = torch.cuda.current_stream(dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -110,7 +140,9 @@ def main():
     print(f"[bench] timed {args.steps} sweeps: wall {wall:.3f}s, kernel ms {kern_ms.round(2)}",
           file=sys.stderr, flush=True)
     st2 = stats.cpu().numpy().view(np.uint64)
-    assert int(st2[:, 0].sum() + st2[:, 1].sum()) == steps_per_sweep
+    steps_per_sweep = int(st2[:, 0].sum() + st2[:, 1].sum())
+    # every sweep of the same inputs and seed takes the same steps
+    assert warm_steps is None or warm_steps == steps_per_sweep
     assert int(out.min().item()) >= 0
     ms_per_step = wall * 1000.0 / args.steps
     value = steps_per_sweep * args.steps / wall
@@ -126,14 +158,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name} FP64 plain sweep", "n_traj": T, "n_species": N,
+        "config": {"workload": f"{w.name} {args.precision.upper()} plain sweep", "n_traj": T, "n_species": N,
                    "n_reactions": M, "t_end": float(w.times[-1]), "n_samples": S,
                    "eps": w.eps, "n_c": w.n_c, "seed": w.seed,
                    "steps_per_sweep": steps_per_sweep,
-                   "leaps": int(st[:, 0].sum()), "ssa_events": int(st[:, 1].sum()),
-                   "rejections": int(st[:, 2].sum())},
+                   "leaps": int(st2[:, 0].sum()), "ssa_events": int(st2[:, 1].sum()),
+                   "rejections": int(st2[:, 2].sum())},
         "latency_ms": {"p50": float(np.percentile(kern_ms, 50)),
                        "p99": float(np.percentile(kern_ms, 99))},
     }
@@ -159,12 +191,13 @@ def main():
     result["cpu_baseline"] = cpu
 
     kern_s = float(np.mean(kern_ms)) / 1000.0
-    if ops_per_step is not None:
+    if ops_per_step is not None and args.precision == "fp64":
         achieved = ops_per_step * steps_per_sweep / kern_s
         result["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                               "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
-                              "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                              "kernel": "sweep_kernel<256>",
+                              "frac": achieved / PEAK_LANE_OPS,
+                              "traffic": measured_traffic() if T == 65536 else None,
+                              "kernel": f"sweep_kernel<256, {rate_segments(M)}, double>",
                               "ops_per_step": ops_per_step,
                               "kernel_ms": float(np.mean(kern_ms))}
     else:

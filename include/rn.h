@@ -41,7 +41,9 @@ extern "C" {
 #define RN_METHOD_TAULEAP 0 /* CGP tau-leaping with critical reactions and SSA bursts */
 #define RN_METHOD_SSA 1     /* exact SSA events only (Gillespie direct method)        */
 
-#define RN_FP64 0 /* all of the method's arithmetic in double precision */
+#define RN_FP64 0 /* all of the method's arithmetic in double precision                  */
+#define RN_FP32 1 /* single-precision propensities, SSA events, tau' and Poisson means;
+                     double precision for time, the SSA-switch test and the critical race */
 
 /*
  * Network description (host memory, caller-owned, copied by rn_load_network).
@@ -113,7 +115,20 @@ int rn_sample_times(double t_end, int32_t n_points, double *out);
  *               tau' >= ssa_factor / a0 (>= 0); ssa_burst: exact events per
  *               burst (>= 1); max_steps: per-trajectory cap on leaps + SSA
  *               events + rejections (>= 1).
- *  method       RN_METHOD_TAULEAP or RN_METHOD_SSA; precision RN_FP64.
+ *  method       RN_METHOD_TAULEAP or RN_METHOD_SSA.
+ *  precision    RN_FP64: every step in double precision (trajectories are a
+ *               deterministic function of the inputs and the seed).
+ *               RN_FP32: rates are rounded to float on load; propensities, the
+ *               SSA event (a0, waiting time, selection), the leap-condition
+ *               bound tau', the Poisson means and the small-mean inversion
+ *               sampler run in float with 24-bit uniforms (the top 24 bits of
+ *               the word pair that RN_FP64 uses for the same draw); time, the
+ *               sample times, a0 of the SSA-switch test, the critical race
+ *               (a0c, tau'' and its selection), the leap length and the PTRS and
+ *               Langevin samplers stay in double.  The same seed gives the same
+ *               random path in both modes until a float rounding changes a
+ *               decision, so FP32 results agree with FP64 in distribution, not
+ *               bit for bit.
  *
  * Buffers are caller-owned and must not overlap.  The call only validates the
  * arguments it can see on the host and enqueues kernels on `hip_stream` (a

@@ -289,7 +289,7 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   if (!(a->ssa_factor >= 0.0)) return RN_E_INVALID_ARG;
   if (a->ssa_burst < 1 || a->max_steps < 1) return RN_E_INVALID_ARG;
   if (a->method != RN_METHOD_TAULEAP && a->method != RN_METHOD_SSA) return RN_E_INVALID_ARG;
-  if (a->precision != RN_FP64) return RN_E_INVALID_ARG;
+  if (a->precision != RN_FP64 && a->precision != RN_FP32) return RN_E_INVALID_ARG;
   if (!(a->cle_threshold == 0.0 || (a->cle_threshold >= 10.0 && a->cle_threshold <= 1e300)))
     return RN_E_INVALID_ARG;
   if (a->n_traj == 0) return RN_OK;
@@ -341,7 +341,8 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   p.method = a->method;
   p.cle_threshold = a->cle_threshold;
   p.theta = sched_theta();
-  e = rn::launch_sweep(p, cfg, (hipStream_t)hip_stream);
+  e = a->precision == RN_FP32 ? rn::launch_sweep_f32(p, cfg, (hipStream_t)hip_stream)
+                              : rn::launch_sweep_f64(p, cfg, (hipStream_t)hip_stream);
   if (e != hipSuccess) return device_error(e);
   return RN_OK;
 }

@@ -1,7 +1,7 @@
 // rn_kernel.h -- packed device tables and kernel parameters of the sweep kernels.
 //
 // Internal to the library (host code in rn_host.cpp fills these, the kernels in
-// rn_sweep.hip read them).  Every table is read with wave-uniform indices, so the
+// rn_sweep_kernel.h, rn_ode.hip and rn_moments.hip read them).  Every table is read with wave-uniform indices, so the
 // kernels fetch them through the scalar data cache.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -107,7 +107,8 @@ inline size_t lds_words_per_lane(int N, int M) {
   return 2 * (size_t)(N + 1) + (size_t)((M + 31) / 32);
 }
 
-hipError_t launch_sweep(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_sweep_f64(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_sweep_f32(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
                           int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream);

@@ -1,9 +1,22 @@
-// rn_sweep.hip -- gfx950 kernels: one wave64 lane per trajectory of a parameter
-// sweep, each advanced by Cao-Gillespie-Petzold tau-leaping (J. Chem. Phys. 124,
-// 044109, 2006) with critical reactions (J. Chem. Phys. 123, 054104, 2005) and
-// bursts of exact SSA events (Gillespie's direct method, 1977).  The model is the
-// paper's (Methods section): X(t) counts molecules per species and every firing
-// adds the reaction's stoichiometric vector.
+// rn_sweep_kernel.h -- gfx950 kernels: one wave64 lane per trajectory of a
+// parameter sweep, each advanced by Cao-Gillespie-Petzold tau-leaping (J. Chem.
+// Phys. 124, 044109, 2006) with critical reactions (J. Chem. Phys. 123, 054104,
+// 2005) and bursts of exact SSA events (Gillespie's direct method, 1977).  The
+// model is the paper's (Methods section): X(t) counts molecules per species and
+// every firing adds the reaction's stoichiometric vector.
+//
+// The kernel template is instantiated once per arithmetic precision R, each in
+// its own translation unit (rn_sweep_f64.hip, rn_sweep_f32.hip):
+//  * R = double: every step in FP64.
+//  * R = float: propensities, the SSA event (sum, waiting time, selection), the
+//    leap-condition bound tau', the Poisson means and the inversion sampler in
+//    FP32 with 24-bit uniforms; FP64 for the time t, the sample times, a0 of the
+//    SSA-switch test, the critical race (a0c, tau'', its selection) and the
+//    leap length tau, and for the PTRS and Langevin samplers (their acceptance
+//    test and increment subtract terms of size lam log lam that FP32 cannot
+//    resolve once lam exceeds about 1e4).  Each FP32 uniform is the top 24 bits
+//    of the word pair the FP64 path uses for the same draw, so the two modes
+//    follow the same random path until an FP32 rounding changes a decision.
 //
 // Layout
 //  * Counts: LDS, lane-minor.  Each lane owns two buffers of N+1 words (current
@@ -19,6 +32,7 @@
 // Each loop iteration runs every phase that some lane of the wave needs, masked
 // to those lanes.  Counter-based random numbers make each trajectory's result
 // independent of how its steps interleave with other lanes'.
+#pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -69,16 +83,55 @@ __device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
   return (double)z * 0x1p-53;
 }
 
+// Uniform on [0,1) with 24 random bits: the top 24 bits of hi times 2^-24.
+__device__ __forceinline__ float u24(uint32_t hi) { return (float)(hi >> 8) * 0x1p-24f; }
+
+template <typename R>
+struct Real;
+template <>
+struct Real<double> {
+  static constexpr bool kF64 = true;
+  __device__ static __forceinline__ double uni(uint32_t hi, uint32_t lo) { return u53(hi, lo); }
+  __device__ static __forceinline__ double log_(double x) { return log(x); }
+  __device__ static __forceinline__ double exp_(double x) { return exp(x); }
+  __device__ static __forceinline__ double abs_(double x) { return fabs(x); }
+};
+template <>
+struct Real<float> {
+  static constexpr bool kF64 = false;
+  __device__ static __forceinline__ float uni(uint32_t hi, uint32_t) { return u24(hi); }
+  __device__ static __forceinline__ float log_(float x) { return logf(x); }
+  __device__ static __forceinline__ float exp_(float x) { return expf(x); }
+  __device__ static __forceinline__ float abs_(float x) { return fabsf(x); }
+};
+template <typename R>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(16)));
+};
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(16)));
+};
+
 // Poisson(lam) for 0 < lam < 10: walk the CDF from k = 0 with one uniform,
-// p_k = p_{k-1} * (lam * (1/k)).
-__device__ __forceinline__ uint32_t poisson_inversion(double lam, double u) {
-  double pk = exp(-lam);
-  double F = pk;
+// p_k = p_{k-1} * (lam * (1/k)).  In FP32 the walk also stops once a term no
+// longer changes F (the CDF has saturated below u; the mass left is below the
+// 24-bit resolution of u).
+template <typename R>
+__device__ __forceinline__ uint32_t poisson_inversion(R lam, R u) {
+  R pk = Real<R>::exp_(-lam);
+  R F = pk;
   int k = 0;
   while (u > F && k < kInvMax) {
     k = k + 1;
-    pk = pk * (lam * (1.0 / (double)k));
-    F = F + pk;
+    pk = pk * (lam * (R(1) / (R)k));
+    const R Fn = F + pk;
+    if constexpr (!Real<R>::kF64) {
+      if (Fn == F) break;
+    }
+    F = Fn;
   }
   return (uint32_t)k;
 }
@@ -140,13 +193,15 @@ __device__ __noinline__ uint32_t cle_count(double lam, uint32_t traj, uint32_t n
   return clamp_draw(kf);
 }
 
-__device__ __forceinline__ uint32_t poisson(double lam, uint32_t hi, uint32_t lo, uint32_t traj,
+template <typename R>
+__device__ __forceinline__ uint32_t poisson(R lam, uint32_t hi, uint32_t lo, uint32_t traj,
                                             uint32_t n, uint32_t j, uint32_t k0, uint32_t k1,
                                             const double* lfact, double cle) {
-  if (!(lam > 0.0)) return 0u;
-  if (lam < 10.0) return poisson_inversion(lam, u53(hi, lo));
-  if (cle > 0.0 && lam >= cle) return cle_count(lam, traj, n, j, k0, k1);
-  return poisson_ptrs(lam, traj, n, j, k0, k1, lfact);
+  if (!(lam > R(0))) return 0u;
+  if (lam < R(10)) return poisson_inversion<R>(lam, Real<R>::uni(hi, lo));
+  const double ld = (double)lam;
+  if (cle > 0.0 && ld >= cle) return cle_count(ld, traj, n, j, k0, k1);
+  return poisson_ptrs(ld, traj, n, j, k0, k1, lfact);
 }
 
 // Network tables are read-only for the whole kernel and indexed wave-uniformly;
@@ -167,25 +222,24 @@ __device__ __forceinline__ TauSpecies rs_at(const TauSpecies* base, int r) {
 }
 
 // Mass-action combinatorial factor h = A * B (halved for a homodimer, where
-// B = A - 1), each count converted exactly to double.
-__device__ __forceinline__ double hval(int32_t A, int32_t B, int32_t dimer) {
-  const double scale = dimer ? 0.5 : 1.0;  // wave-uniform; 1.0 * h == h exactly
-  return scale * ((double)A * (double)B);
+// B = A - 1), each count converted to R (exactly, for double).
+template <typename R>
+__device__ __forceinline__ R hval(int32_t A, int32_t B, int32_t dimer) {
+  const R scale = dimer ? R(0.5) : R(1);  // wave-uniform; 1 * h == h exactly
+  return scale * ((R)A * (R)B);
 }
-
-typedef double v16d __attribute__((ext_vector_type(16)));
 
 // Element j (wave-uniform, LO <= j < HI) of a register array, by binary search
 // over compile-time indices, so the array never needs a dynamic register index.
-template <int LO, int HI, int NS>
+template <int LO, int HI, int NS, typename R>
 struct PickReg {
-  __device__ static __forceinline__ double get(const double (&v)[NS], int j) {
+  __device__ static __forceinline__ R get(const R (&v)[NS], int j) {
     if constexpr (HI - LO == 1) {
       return v[LO];
     } else {
       constexpr int MID = (LO + HI) / 2;
-      if (j < MID) return PickReg<LO, MID, NS>::get(v, j);
-      return PickReg<MID, HI, NS>::get(v, j);
+      if (j < MID) return PickReg<LO, MID, NS, R>::get(v, j);
+      return PickReg<MID, HI, NS, R>::get(v, j);
     }
   }
 };
@@ -193,7 +247,7 @@ struct PickReg {
 // WG lanes per workgroup.  NSEG > 0: the lane's rate constants are held in
 // 16 * NSEG registers (M <= 16 * NSEG); NSEG == 0: they are read from the rates
 // array.
-template <int WG, int NSEG>
+template <int WG, int NSEG, typename R>
 __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   extern __shared__ int32_t lds[];
   const DevNet& g = p.net;
@@ -222,15 +276,18 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   // constants (every pass over them is unrolled), so each is an ordinary
   // register; random access goes through a compare tree (rate_at).
   constexpr int RMAX = NSEG > 0 ? 16 * NSEG : 1;
-  double c[RMAX];
+  typedef typename Vec16<R>::type V16;
+  R c[RMAX];
 #pragma unroll
   for (int j = 0; j < RMAX; ++j)
-    c[j] = (NSEG > 0 && valid && j < g.M_real) ? crate[(int64_t)j * rld] : 0.0;
+    c[j] = (NSEG > 0 && valid && j < g.M_real) ? (R)crate[(int64_t)j * rld] : R(0);
+  // c_j of the rates array, for the NSEG == 0 form.
+  auto mrate = [&](int j) -> R { return (R)crate[(int64_t)j * rld]; };
 
   // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
-  auto prop = [&](int j, double cj) -> double {
+  auto prop = [&](int j, R cj) -> R {
     const RateLaw L = law_at(g.law, j);
-    return cj * hval(xc[L.ia * WG], xc[L.ib * WG] + L.db, L.dimer);
+    return cj * hval<R>(xc[L.ia * WG], xc[L.ib * WG] + L.db, L.dimer);
   };
   // f(j, c_j, a_j) for j = 0..M-1 in order, a_j being the current propensity.
   // more() is a wave-uniform "keep going" vote polled every four reactions (f
@@ -239,7 +296,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   // register rates the walk is fully unrolled (M is a multiple of 16: null
   // reactions pad the last group).
   auto each_rate = [&](auto&& f, auto&& more) {
-    auto group = [&](int j0, double q0, double q1, double q2, double q3) {
+    auto group = [&](int j0, R q0, R q1, R q2, R q3) {
       // The table is invariant; hiding the base pointer's value keeps the
       // compiler from hoisting every group's rate laws out of the loops (which
       // would pin hundreds of scalar registers).
@@ -251,19 +308,18 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
       const int32_t A1 = xc[L1.ia * WG], B1 = xc[L1.ib * WG];
       const int32_t A2 = xc[L2.ia * WG], B2 = xc[L2.ib * WG];
       const int32_t A3 = xc[L3.ia * WG], B3 = xc[L3.ib * WG];
-      f(j0, q0, q0 * hval(A0, B0 + L0.db, L0.dimer));
-      f(j0 + 1, q1, q1 * hval(A1, B1 + L1.db, L1.dimer));
-      f(j0 + 2, q2, q2 * hval(A2, B2 + L2.db, L2.dimer));
-      f(j0 + 3, q3, q3 * hval(A3, B3 + L3.db, L3.dimer));
+      f(j0, q0, q0 * hval<R>(A0, B0 + L0.db, L0.dimer));
+      f(j0 + 1, q1, q1 * hval<R>(A1, B1 + L1.db, L1.dimer));
+      f(j0 + 2, q2, q2 * hval<R>(A2, B2 + L2.db, L2.dimer));
+      f(j0 + 3, q3, q3 * hval<R>(A3, B3 + L3.db, L3.dimer));
     };
     if constexpr (NSEG == 0) {
       int j = 0;
       for (; j + 4 <= M; j += 4) {
-        group(j, crate[(int64_t)j * rld], crate[(int64_t)(j + 1) * rld],
-              crate[(int64_t)(j + 2) * rld], crate[(int64_t)(j + 3) * rld]);
+        group(j, mrate(j), mrate(j + 1), mrate(j + 2), mrate(j + 3));
         if (!more()) return;
       }
-      for (; j < M; ++j) f(j, crate[(int64_t)j * rld], prop(j, crate[(int64_t)j * rld]));
+      for (; j < M; ++j) f(j, mrate(j), prop(j, mrate(j)));
     } else {
 #pragma unroll
       for (int j = 0; j < RMAX; j += 4) {
@@ -274,9 +330,9 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   };
   auto always = []() { return true; };
   // c_j for one wave-uniform j.
-  auto rate_at = [&](int j) -> double {
-    if constexpr (NSEG == 0) return crate[(int64_t)j * rld];
-    else return PickReg<0, RMAX, RMAX>::get(c, j);
+  auto rate_at = [&](int j) -> R {
+    if constexpr (NSEG == 0) return mrate(j);
+    else return PickReg<0, RMAX, RMAX, R>::get(c, j);
   };
 
   for (int i = 0; i < N; ++i) {
@@ -347,22 +403,22 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
     if (mode == kSsa) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
-        double sum = 0.0;
-        each_rate([&](int, double, double a) { sum = sum + a; }, always);
-        if (sum == 0.0) { finish(kStAbsorbed); break; }
+        R sum = R(0);
+        each_rate([&](int, R, R a) { sum = sum + a; }, always);
+        if (sum == R(0)) { finish(kStAbsorbed); break; }
         const Words w = philox10(traj, n, 0u, kStreamEvent, k0, k1);
-        const double tau = -log(1.0 - u53(w.w0, w.w1)) / sum;
-        const double tn = t + tau;
+        const R tau = -Real<R>::log_(R(1) - Real<R>::uni(w.w0, w.w1)) / sum;
+        const double tn = t + (double)tau;
         while (s < S && t_next < tn) record_next();
         if (s == S) { mode = kDone; break; }
-        const double r = u53(w.w2, w.w3) * sum;
-        double acc = 0.0;
+        const R r = Real<R>::uni(w.w2, w.w3) * sum;
+        R acc = R(0);
         int pick = -1, last = -1;
         each_rate(
-            [&](int j, double, double a) {
+            [&](int j, R, R a) {
               if (pick < 0) {
                 acc = acc + a;
-                if (a > 0.0) last = j;
+                if (a > R(0)) last = j;
                 if (r < acc) pick = j;
               }
             },
@@ -395,11 +451,11 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
     if (mode == kDecide) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
-        double sum = 0.0;
+        double sum = 0.0;  // FP64 in both precisions: it feeds the SSA-switch test
         uint32_t bits = 0;
-        each_rate([&](int j, double, double a) {
-          sum = sum + a;
-          if (a > 0.0) {
+        each_rate([&](int j, R, R a) {
+          sum = sum + (double)a;
+          if (a > R(0)) {
             bool cr = false;
             const int e1 = cld(g.cons_ptr, j + 1);
             for (int e = cld(g.cons_ptr, j); e < e1; ++e) {
@@ -415,30 +471,31 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         }, always);
         a0 = sum;
         if (sum == 0.0) { finish(kStAbsorbed); break; }
-        double tp = __builtin_inf();
+        R tp = (R)__builtin_inf();
+        const R eps = (R)p.eps;
         for (int r = 0; r < g.n_rs; ++r) {
           const TauSpecies ts = rs_at(g.rs, r);
-          double mu = 0.0, sig = 0.0;
+          R mu = R(0), sig = R(0);
           for (int e = ts.begin; e < ts.end; ++e) {
             const int2 en = cld2(g.rs_ent, e);
             if (critbit(en.x)) continue;
-            const double a = prop(en.x, rate_at(en.x));
-            mu = mu + (double)en.y * a;
-            sig = sig + (double)(en.y * en.y) * a;
+            const R a = prop(en.x, rate_at(en.x));
+            mu = mu + (R)en.y * a;
+            sig = sig + (R)(en.y * en.y) * a;
           }
           const int32_t xi = xc[ts.species * WG];
-          double bnd = 1.0;
+          R bnd = R(1);
           if (xi > 1) {
-            const double gi = ts.gkind == 1 ? 1.0
-                              : ts.gkind == 2 ? 2.0
-                                              : 2.0 + 1.0 / (double)(xi - 1);
-            bnd = p.eps * (double)xi / gi;
-            if (bnd < 1.0) bnd = 1.0;
+            const R gi = ts.gkind == 1 ? R(1)
+                         : ts.gkind == 2 ? R(2)
+                                         : R(2) + R(1) / (R)(xi - 1);
+            bnd = eps * (R)xi / gi;
+            if (bnd < R(1)) bnd = R(1);
           }
-          if (mu != 0.0) { const double q = bnd / fabs(mu); if (q < tp) tp = q; }
-          if (sig != 0.0) { const double q = (bnd * bnd) / sig; if (q < tp) tp = q; }
+          if (mu != R(0)) { const R q = bnd / Real<R>::abs_(mu); if (q < tp) tp = q; }
+          if (sig != R(0)) { const R q = (bnd * bnd) / sig; if (q < tp) tp = q; }
         }
-        tau_p = tp;
+        tau_p = (double)tp;
         mode = kLeap;
       } while (false);
     }
@@ -460,7 +517,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
 #pragma unroll 1
           for (int j = 0; j < M; ++j) {
             if ((j & 31) == 0) cw = (uint32_t)crit[(j >> 5) * WG];
-            if ((cw >> (j & 31)) & 1u) a0c = a0c + prop(j, rate_at(j));
+            if ((cw >> (j & 31)) & 1u) a0c = a0c + (double)prop(j, rate_at(j));
           }
         }
         Words ev = {0u, 0u, 0u, 0u};
@@ -484,19 +541,21 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
         // a time: their means go into one fresh register vector, then a rolled
         // loop draws them in pairs, the two reactions of a pair sharing one
         // Philox block of the first-uniform stream.
-        auto draw_block = [&](int base, v16d lam) {
+        const R taur = (R)tau;
+        auto draw_block = [&](int base, V16 lam) {
 #pragma unroll 1
           for (int e = 0; e < 16; e += 2) {
             const int je = base + e;
             if (je >= M) break;
             const bool two = je + 1 < M;
-            const double le = lam[e], lo = lam[e + 1];
+            const R le = lam[e], lo = lam[e + 1];
             Words w = {0u, 0u, 0u, 0u};
-            if ((le > 0.0 && le < 10.0) || (lo > 0.0 && lo < 10.0))
+            if ((le > R(0) && le < R(10)) || (lo > R(0) && lo < R(10)))
               w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
-            const uint32_t d0 = poisson(le, w.w0, w.w1, traj, n, (uint32_t)je, k0, k1, g.log_fact, p.cle_threshold);
-            const uint32_t d1 =
-                poisson(lo, w.w2, w.w3, traj, n, (uint32_t)(je + 1), k0, k1, g.log_fact, p.cle_threshold);
+            const uint32_t d0 = poisson<R>(le, w.w0, w.w1, traj, n, (uint32_t)je, k0, k1,
+                                           g.log_fact, p.cle_threshold);
+            const uint32_t d1 = poisson<R>(lo, w.w2, w.w3, traj, n, (uint32_t)(je + 1), k0, k1,
+                                           g.log_fact, p.cle_threshold);
             if (__any(d0 != 0u)) apply(xn, je, (int32_t)d0);
             kabs += (uint64_t)d0 * (uint32_t)cld(g.nu_abs, je);
             if (two) {
@@ -509,7 +568,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
 #pragma unroll
           for (int base = 0; base < RMAX; base += 16) {
             const uint32_t cw = (uint32_t)crit[(base >> 5) * WG] >> (base & 31);
-            v16d lam;
+            V16 lam;
 #pragma unroll
             for (int e = 0; e < 16; e += 4) {
               const int j0 = base + e;
@@ -521,23 +580,26 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
               const int32_t A1 = xc[L1.ia * WG], B1 = xc[L1.ib * WG];
               const int32_t A2 = xc[L2.ia * WG], B2 = xc[L2.ib * WG];
               const int32_t A3 = xc[L3.ia * WG], B3 = xc[L3.ib * WG];
-              lam[e] = ((cw >> e) & 1u) ? 0.0 : c[j0] * hval(A0, B0 + L0.db, L0.dimer) * tau;
-              lam[e + 1] =
-                  ((cw >> (e + 1)) & 1u) ? 0.0 : c[j0 + 1] * hval(A1, B1 + L1.db, L1.dimer) * tau;
-              lam[e + 2] =
-                  ((cw >> (e + 2)) & 1u) ? 0.0 : c[j0 + 2] * hval(A2, B2 + L2.db, L2.dimer) * tau;
-              lam[e + 3] =
-                  ((cw >> (e + 3)) & 1u) ? 0.0 : c[j0 + 3] * hval(A3, B3 + L3.db, L3.dimer) * tau;
+              lam[e] = ((cw >> e) & 1u) ? R(0) : c[j0] * hval<R>(A0, B0 + L0.db, L0.dimer) * taur;
+              lam[e + 1] = ((cw >> (e + 1)) & 1u)
+                               ? R(0)
+                               : c[j0 + 1] * hval<R>(A1, B1 + L1.db, L1.dimer) * taur;
+              lam[e + 2] = ((cw >> (e + 2)) & 1u)
+                               ? R(0)
+                               : c[j0 + 2] * hval<R>(A2, B2 + L2.db, L2.dimer) * taur;
+              lam[e + 3] = ((cw >> (e + 3)) & 1u)
+                               ? R(0)
+                               : c[j0 + 3] * hval<R>(A3, B3 + L3.db, L3.dimer) * taur;
             }
             draw_block(base, lam);
           }
         } else {
           for (int base = 0; base < M; base += 16) {
-            v16d lam;
+            V16 lam;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
               const int j = base + e;
-              lam[e] = (j < M && !critbit(j)) ? prop(j, crate[(int64_t)j * rld]) * tau : 0.0;
+              lam[e] = (j < M && !critbit(j)) ? prop(j, mrate(j)) * taur : R(0);
             }
             draw_block(base, lam);
           }
@@ -552,7 +614,7 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
           for (int j = 0; j < M && __any(jc < 0); ++j) {
             if ((j & 31) == 0) cw2 = (uint32_t)crit[(j >> 5) * WG];
             if (jc < 0 && ((cw2 >> (j & 31)) & 1u)) {
-              const double a = prop(j, rate_at(j));
+              const double a = (double)prop(j, rate_at(j));
               acc = acc + a;
               if (a > 0.0) last = j;
               if (r < acc) jc = j;
@@ -579,13 +641,14 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
               if (critbit(j)) {
                 kj = (fire && j == jc) ? 1 : 0;
               } else {
-                const double lam = prop(j, rate_at(j)) * tau;
+                const R lam = prop(j, rate_at(j)) * taur;
                 Words w = {0u, 0u, 0u, 0u};
-                if (lam > 0.0 && lam < 10.0)
+                if (lam > R(0) && lam < R(10))
                   w = philox10(traj, n, (uint32_t)(j >> 1), kStreamFirst, k0, k1);
                 const uint32_t hi = (j & 1) ? w.w2 : w.w0;
                 const uint32_t lo = (j & 1) ? w.w3 : w.w1;
-                kj = poisson(lam, hi, lo, traj, n, (uint32_t)j, k0, k1, g.log_fact, p.cle_threshold);
+                kj = poisson<R>(lam, hi, lo, traj, n, (uint32_t)j, k0, k1, g.log_fact,
+                                p.cle_threshold);
               }
               acc += kj * (int64_t)en.y;
             }
@@ -623,42 +686,43 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   }
 }
 
-template <int WG, int NSEG>
+template <int WG, int NSEG, typename R>
 hipError_t launch_one(const SweepParams& p, size_t lds, hipStream_t stream, int64_t blocks) {
-  hipError_t err = hipFuncSetAttribute((const void*)sweep_kernel<WG, NSEG>,
+  hipError_t err = hipFuncSetAttribute((const void*)sweep_kernel<WG, NSEG, R>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((sweep_kernel<WG, NSEG>), dim3((unsigned)blocks), dim3(WG), lds, stream, p);
+  hipLaunchKernelGGL((sweep_kernel<WG, NSEG, R>), dim3((unsigned)blocks), dim3(WG), lds, stream,
+                     p);
   return hipGetLastError();
 }
 
-template <int WG>
+template <int WG, typename R>
 hipError_t launch_wg(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream,
                      int64_t blocks) {
   switch (cfg.rate_segs) {
-    case 1: return launch_one<WG, 1>(p, cfg.lds_bytes, stream, blocks);
-    case 2: return launch_one<WG, 2>(p, cfg.lds_bytes, stream, blocks);
-    case 3: return launch_one<WG, 3>(p, cfg.lds_bytes, stream, blocks);
-    case 4: return launch_one<WG, 4>(p, cfg.lds_bytes, stream, blocks);
-    case 5: return launch_one<WG, 5>(p, cfg.lds_bytes, stream, blocks);
-    case 6: return launch_one<WG, 6>(p, cfg.lds_bytes, stream, blocks);
-    case 7: return launch_one<WG, 7>(p, cfg.lds_bytes, stream, blocks);
-    case 8: return launch_one<WG, 8>(p, cfg.lds_bytes, stream, blocks);
-    case 0: return launch_one<WG, 0>(p, cfg.lds_bytes, stream, blocks);
+    case 1: return launch_one<WG, 1, R>(p, cfg.lds_bytes, stream, blocks);
+    case 2: return launch_one<WG, 2, R>(p, cfg.lds_bytes, stream, blocks);
+    case 3: return launch_one<WG, 3, R>(p, cfg.lds_bytes, stream, blocks);
+    case 4: return launch_one<WG, 4, R>(p, cfg.lds_bytes, stream, blocks);
+    case 5: return launch_one<WG, 5, R>(p, cfg.lds_bytes, stream, blocks);
+    case 6: return launch_one<WG, 6, R>(p, cfg.lds_bytes, stream, blocks);
+    case 7: return launch_one<WG, 7, R>(p, cfg.lds_bytes, stream, blocks);
+    case 8: return launch_one<WG, 8, R>(p, cfg.lds_bytes, stream, blocks);
+    case 0: return launch_one<WG, 0, R>(p, cfg.lds_bytes, stream, blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
+hipError_t launch_sweep_prec(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream) {
+  const int64_t blocks = (p.n_traj + cfg.wg - 1) / cfg.wg;
+  if (blocks <= 0) return hipSuccess;
+  switch (cfg.wg) {
+    case 64: return launch_wg<64, R>(p, cfg, stream, blocks);
+    case 256: return launch_wg<256, R>(p, cfg, stream, blocks);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
-
-hipError_t launch_sweep(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream) {
-  const int64_t blocks = (p.n_traj + cfg.wg - 1) / cfg.wg;
-  if (blocks <= 0) return hipSuccess;
-  switch (cfg.wg) {
-    case 64: return launch_wg<64>(p, cfg, stream, blocks);
-    case 256: return launch_wg<256>(p, cfg, stream, blocks);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 }  // namespace rn

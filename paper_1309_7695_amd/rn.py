@@ -23,7 +23,8 @@ RN_E_NOMEM = -4
 RN_E_DEVICE = -5
 ST_ABSORBED, ST_MAXSTEPS, ST_OVERFLOW = 1, 2, 4
 METHOD_TAULEAP, METHOD_SSA = 0, 1
-FP64 = 0
+FP64, FP32 = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
            "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_moments", "rn_ode_args_init",
@@ -166,15 +167,18 @@ class Network:
 
 def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
           n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
-          cle_threshold=0.0, stream=None):
+          cle_threshold=0.0, precision="fp64", stream=None):
     """Enqueue ``rn_sweep`` on ``stream`` (default: torch's current stream).
 
     ``rates`` float64 [M][>=T] (row stride = ld), ``x0`` int32 [N] or [N][>=T],
     ``times`` float64 [S], ``out`` int32 [S][N][>=T] (last dim stride = ld),
     ``stats`` uint64/int64 [T][4]; all CUDA (HIP) tensors on the network's
-    device.  T is taken from ``stats``.  Returns immediately."""
+    device.  T is taken from ``stats``.  ``precision`` is "fp64" or "fp32"
+    (RN_FP64 / RN_FP32).  Returns immediately."""
     import torch
 
+    if precision not in PRECISIONS:
+        raise ValueError("precision must be 'fp64' or 'fp32'")
     T = int(stats.shape[0])
     for name, t in (("rates", rates), ("x0", x0), ("times", times), ("out", out),
                     ("stats", stats)):
@@ -216,7 +220,7 @@ def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, ep
     a.seed = int(seed) & (2**64 - 1)
     a.eps, a.n_c, a.ssa_factor = float(eps), int(n_c), float(ssa_factor)
     a.ssa_burst, a.max_steps, a.method, a.precision = int(ssa_burst), int(max_steps), \
-        int(method), FP64
+        int(method), PRECISIONS[precision]
     a.cle_threshold = float(cle_threshold)
     if stream is None:
         stream = torch.cuda.current_stream(rates.device)

@@ -65,3 +65,31 @@ def z_var(samples, var):
     m4 = np.mean(d ** 4)
     se = np.sqrt(max(m4 - m2 ** 2, 1e-300) / n)
     return abs(s.var(ddof=1) - var) / se
+
+
+def ensemble_z(a, b):
+    """Per-cell z statistics between two independent ensembles.
+
+    ``a`` and ``b`` are [S][N][T] sample arrays (trajectories last).  For every
+    (sample, species) cell: z of the difference of means, sqrt(v_a/n_a + v_b/n_b)
+    as its standard error, and z of the difference of the unbiased variances,
+    each variance's standard error taken from its fourth central moment.
+    Returns (z_mean [S][N], z_var [S][N], both_constant [S][N]); cells where both
+    ensembles are constant get z = 0 when they agree and inf when not."""
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    na, nb = a.shape[-1], b.shape[-1]
+    ma, mb = a.mean(-1), b.mean(-1)
+    da, db = a - ma[..., None], b - mb[..., None]
+    m2a, m2b = np.mean(da ** 2, -1), np.mean(db ** 2, -1)
+    m4a, m4b = np.mean(da ** 4, -1), np.mean(db ** 4, -1)
+    va, vb = m2a * na / (na - 1), m2b * nb / (nb - 1)
+    const = (m2a == 0) & (m2b == 0)
+    se_m = np.sqrt(va / na + vb / nb)
+    se_v = np.sqrt(np.maximum(m4a - m2a ** 2, 0) / na + np.maximum(m4b - m2b ** 2, 0) / nb)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        zm = np.where(se_m > 0, np.abs(ma - mb) / se_m, 0.0)
+        zv = np.where(se_v > 0, np.abs(va - vb) / se_v, 0.0)
+    zm = np.where(const, np.where(ma == mb, 0.0, np.inf), zm)
+    zv = np.where(const, 0.0, zv)
+    return zm, zv, const

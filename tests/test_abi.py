@@ -125,3 +125,19 @@ def test_binding_refuses_host_tensors():
     z = torch.zeros(1)
     with pytest.raises(ValueError):
         rn.sweep(Fake(), z, z, z, z, torch.zeros((1, 4), dtype=torch.int64), seed=1)
+
+
+def test_precision_constants_match_header():
+    import re
+    text = open(os.path.join(ROOT, "include", "rn.h")).read()
+    consts = dict(re.findall(r"#define (RN_FP\d\d) (\d+)", text))
+    assert int(consts["RN_FP64"]) == rn.FP64 == rn.PRECISIONS["fp64"]
+    assert int(consts["RN_FP32"]) == rn.FP32 == rn.PRECISIONS["fp32"]
+
+
+def test_binding_refuses_unknown_precision():
+    import torch
+    z = torch.zeros(1)
+    with pytest.raises(ValueError):
+        rn.sweep(None, z, z, z, z, torch.zeros((1, 4), dtype=torch.int64), seed=1,
+                 precision="fp16")

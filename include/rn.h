@@ -171,6 +171,19 @@ void rn_sweep_args_init(rn_sweep_args *args);
 int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream);
 
 /*
+ * Which kernel rn_sweep runs for this network, precision and n_traj.
+ * Networks with at most 63 species and 128 reactions get a kernel compiled for
+ * that network (hipRTC, on first use, then cached for the process): its counts,
+ * rate constants and tables are compile-time values in registers, and it gives
+ * the same results as the generic kernel, which runs otherwise (also when the
+ * environment sets RN_JIT=0 or the compilation fails).  The first rn_sweep of a
+ * network and precision pays the compilation on the calling thread.
+ * Returns 1 (network-compiled; compiling it now if needed), 0 (generic), or
+ * RN_E_INVALID_ARG / RN_E_DEVICE.
+ */
+int rn_sweep_kernel_kind(const rn_network *net, int32_t precision, int64_t n_traj);
+
+/*
  * Deterministic sweep: the reaction-rate equations that abundant species follow
  * (paper, Methods section: mean-field ODEs, which agree with the stochastic
  * model in the thermodynamic limit),

@@ -13,9 +13,11 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "rn.h"
+#include "rn_jit.h"
 #include "rn_kernel.h"
 
 struct rn_network {
@@ -24,6 +26,7 @@ struct rn_network {
   void* dbuf = nullptr;
   size_t bytes = 0;
   rn::DevNet dev{};
+  std::string jit_consts;  // compile-time prelude of the network-compiled kernel, or empty
 };
 
 namespace {
@@ -57,6 +60,7 @@ struct HostTables {
   std::vector<uint32_t> nu_abs;
   std::vector<rn::TauSpecies> rs;
   std::vector<double> log_fact;
+  std::vector<int32_t> nu_dense;  // [M][jit_dense_ld(N)] for network-compiled kernels
   int32_t crit_words = 0;
 };
 
@@ -159,9 +163,65 @@ int build_tables(const rn_network_desc* d, HostTables& T) {
     T.rs.push_back(ts);
   }
   T.crit_words = (Mp + 31) / 32;
+  if (N <= rn::kJitMaxSpecies && M <= rn::kJitMaxReactions) {
+    const int ld = rn::jit_dense_ld(N);
+    T.nu_dense.assign((size_t)M * ld, 0);
+    for (int32_t j = 0; j < M; ++j)
+      for (auto& sv : nu[j]) T.nu_dense[(size_t)j * ld + sv.first] = sv.second;
+  }
   T.log_fact.resize(rn::kLogFactTable);
   for (int k = 0; k < rn::kLogFactTable; ++k) T.log_fact[k] = std::lgamma((double)k + 1.0);
   return RN_OK;
+}
+
+// The network as compile-time constants for rn_net_kernel.h (namespace rnnet).
+std::string jit_constants(const HostTables& T, int32_t N, int32_t M) {
+  std::string s = "namespace rnnet {\n";
+  auto num = [](long long v) { return std::to_string(v); };
+  s += "constexpr int N = " + num(N) + ";\nconstexpr int M = " + num(M) + ";\n";
+  s += "constexpr int DLD = " + num(rn::jit_dense_ld(N)) + ";\n";
+  auto list1 = [&](const char* type, const char* name, const std::vector<long long>& v) {
+    s += std::string("constexpr ") + type + " " + name + "[] = {";
+    if (v.empty()) s += "0";
+    for (size_t k = 0; k < v.size(); ++k) s += (k ? "," : "") + num(v[k]);
+    s += "};\n";
+  };
+  auto list2 = [&](const char* name, const std::vector<int2>& v, size_t n) {
+    s += std::string("constexpr int ") + name + "[][2] = {";
+    if (n == 0) s += "{0,0}";
+    for (size_t k = 0; k < n; ++k) s += (k ? ",{" : "{") + num(v[k].x) + "," + num(v[k].y) + "}";
+    s += "};\n";
+  };
+  s += "constexpr int LAW[][4] = {";
+  for (int32_t j = 0; j < M; ++j) {
+    const rn::RateLaw& L = T.law[j];
+    s += (j ? ",{" : "{") + num(L.ia) + "," + num(L.ib) + "," + num(L.db) + "," + num(L.dimer) + "}";
+  }
+  s += "};\n";
+  std::vector<long long> v;
+  v.assign(T.nu_ptr.begin(), T.nu_ptr.begin() + M + 1);
+  list1("int", "NU_PTR", v);
+  list2("NU_ENT", T.nu_ent, (size_t)T.nu_ptr[M]);
+  v.assign(T.nu_abs.begin(), T.nu_abs.begin() + M);
+  list1("unsigned", "NU_ABS", v);
+  v.assign(T.cons_ptr.begin(), T.cons_ptr.begin() + M + 1);
+  list1("int", "CONS_PTR", v);
+  list2("CONS_ENT", T.cons_ent, (size_t)T.cons_ptr[M]);
+  s += "constexpr int NRS = " + num((long long)T.rs.size()) + ";\n";
+  s += "constexpr int RS[][4] = {";
+  if (T.rs.empty()) s += "{0,0,0,0}";
+  for (size_t r = 0; r < T.rs.size(); ++r) {
+    const rn::TauSpecies& ts = T.rs[r];
+    s += (r ? ",{" : "{") + num(ts.species) + "," + num(ts.gkind) + "," + num(ts.begin) + "," +
+         num(ts.end) + "}";
+  }
+  s += "};\n";
+  list2("RS_ENT", T.rs_ent, T.rs_ent.size());
+  v.assign(T.col_ptr.begin(), T.col_ptr.end());
+  list1("int", "COL_PTR", v);
+  list2("COL_ENT", T.col_ent, T.col_ent.size());
+  s += "}  // namespace rnnet\n";
+  return s;
 }
 
 // Appends a host array to a packed image, 16-byte aligned; returns its offset.
@@ -238,7 +298,7 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
                o_cons_ent = pack(img, T.cons_ent), o_nu_abs = pack(img, T.nu_abs),
                o_rs = pack(img, T.rs), o_rs_ent = pack(img, T.rs_ent),
                o_col_ptr = pack(img, T.col_ptr), o_col_ent = pack(img, T.col_ent),
-               o_log_fact = pack(img, T.log_fact);
+               o_log_fact = pack(img, T.log_fact), o_nu_dense = pack(img, T.nu_dense);
 
   rn_network* net = new (std::nothrow) rn_network;
   if (!net) return RN_E_NOMEM;
@@ -269,6 +329,14 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
   D.col_ptr = (const int32_t*)(b + o_col_ptr);
   D.col_ent = (const int2*)(b + o_col_ent);
   D.log_fact = (const double*)(b + o_log_fact);
+  D.nu_dense = T.nu_dense.empty() ? nullptr : (const int32_t*)(b + o_nu_dense);
+  if (!T.nu_dense.empty()) {
+    try {
+      net->jit_consts = jit_constants(T, net->N, net->M);
+    } catch (const std::bad_alloc&) {
+      net->jit_consts.clear();
+    }
+  }
   *out = net;
   return RN_OK;
 }
@@ -277,6 +345,13 @@ void rn_free_network(rn_network* net) {
   if (!net) return;
   if (net->dbuf) (void)hipFree(net->dbuf);
   delete net;
+}
+
+// The network-compiled kernel for this handle, precision and workgroup size
+// (compiled on first use), or null when the generic kernels run.
+static hipFunction_t network_kernel(const rn_network* net, int32_t precision, int wg) {
+  if (net->jit_consts.empty() || !rn::jit_enabled()) return nullptr;
+  return rn::jit_kernel(net->jit_consts, precision == RN_FP32 ? rn::kJitFP32 : rn::kJitFP64, wg);
 }
 
 int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
@@ -341,10 +416,29 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   p.method = a->method;
   p.cle_threshold = a->cle_threshold;
   p.theta = sched_theta();
-  e = a->precision == RN_FP32 ? rn::launch_sweep_f32(p, cfg, (hipStream_t)hip_stream)
-                              : rn::launch_sweep_f64(p, cfg, (hipStream_t)hip_stream);
+  const int jwg = a->n_traj >= (int64_t)256 * n_cu ? 256 : 64;
+  if (hipFunction_t fn = network_kernel(net, a->precision, jwg)) {
+    e = rn::jit_launch(fn, p, jwg, rn::jit_lds_bytes(net->N, net->M, jwg),
+                       (hipStream_t)hip_stream);
+  } else {
+    e = a->precision == RN_FP32 ? rn::launch_sweep_f32(p, cfg, (hipStream_t)hip_stream)
+                                : rn::launch_sweep_f64(p, cfg, (hipStream_t)hip_stream);
+  }
   if (e != hipSuccess) return device_error(e);
   return RN_OK;
+}
+
+int rn_sweep_kernel_kind(const rn_network* net, int32_t precision, int64_t n_traj) {
+  if (!net || n_traj < 0 || (precision != RN_FP64 && precision != RN_FP32))
+    return RN_E_INVALID_ARG;
+  int dev = -1, n_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e);
+  if (dev != net->device) return RN_E_INVALID_ARG;
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return device_error(e);
+  const int jwg = n_traj >= (int64_t)256 * n_cu ? 256 : 64;
+  return network_kernel(net, precision, jwg) ? 1 : 0;
 }
 
 void rn_ode_args_init(rn_ode_args* a) {

@@ -1,0 +1,33 @@
+// rn_jit.h -- internal interface of the network-compiled sweep kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "rn_kernel.h"
+
+namespace rn {
+
+constexpr int kJitFP64 = 0, kJitFP32 = 1;
+// Networks whose counts and rates fit the compiled kernel's registers.
+constexpr int kJitMaxSpecies = 63, kJitMaxReactions = 128;
+
+// Row stride (words) of the dense stoichiometry matrix for n species: whole
+// 16-byte vectors plus one more, which moves consecutive rows to other banks.
+inline int jit_dense_ld(int n) { return 4 * ((n + 3) / 4) + 4; }
+
+// LDS of one workgroup: the dense matrix [M][jit_dense_ld(N)] and every lane's
+// N-word leap candidate.
+inline size_t jit_lds_bytes(int n, int m, int wg) {
+  return ((size_t)m * jit_dense_ld(n) + (size_t)n * wg) * sizeof(int32_t);
+}
+
+// False when the environment sets RN_JIT=0 (the generic kernels are used).
+bool jit_enabled();
+// The compiled kernel for a network prelude, compiled on first use; null when
+// hipRTC is unavailable or the compilation fails.
+hipFunction_t jit_kernel(const std::string& consts, int precision, int wg);
+hipError_t jit_launch(hipFunction_t fn, const SweepParams& p, int wg, size_t lds,
+                      hipStream_t stream);
+
+}  // namespace rn

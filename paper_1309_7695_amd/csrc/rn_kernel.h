@@ -4,8 +4,10 @@
 // rn_sweep_kernel.h, rn_ode.hip and rn_moments.hip read them).  Every table is read with wave-uniform indices, so the
 // kernels fetch them through the scalar data cache.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace rn {
 
@@ -40,6 +42,7 @@ struct DevNet {
   const int32_t* col_ptr;    // [N+1] species-major net changes (all species)
   const int2* col_ent;       // {j, nu_ij}, ascending j
   const double* log_fact;    // [kLogFactTable] log(k!) for small k
+  const int32_t* nu_dense;   // [M_real][row stride] dense nu_ij (network-compiled kernels), or null
 };
 
 constexpr int kLogFactTable = 1024;
@@ -92,6 +95,7 @@ struct OdeParams {
   uint64_t max_steps;
 };
 
+#ifndef __HIPCC_RTC__
 // Launch configuration chosen by the host.
 struct LaunchCfg {
   int wg;          // lanes (= trajectories) per workgroup: 64 or 256
@@ -112,5 +116,6 @@ hipError_t launch_sweep_f32(const SweepParams& p, const LaunchCfg& cfg, hipStrea
 hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
                           int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream);
+#endif  // __HIPCC_RTC__
 
 }  // namespace rn

@@ -27,7 +27,8 @@ FP64, FP32 = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
-           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_moments", "rn_ode_args_init",
+           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_sweep_kernel_kind",
+           "rn_moments", "rn_ode_args_init",
            "rn_ode_work_doubles", "rn_ode_sweep", "rn_strerror", "rn_last_device_error"]
 
 
@@ -92,6 +93,8 @@ def lib():
         L.rn_sweep_args_init.restype = None
         L.rn_sweep.argtypes = [C.c_void_p, C.POINTER(SweepArgs), C.c_void_p]
         L.rn_sweep.restype = C.c_int
+        L.rn_sweep_kernel_kind.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+        L.rn_sweep_kernel_kind.restype = C.c_int
         L.rn_moments.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int64,
                                  C.c_void_p, C.c_void_p, C.c_void_p]
         L.rn_moments.restype = C.c_int
@@ -225,6 +228,17 @@ def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, ep
     if stream is None:
         stream = torch.cuda.current_stream(rates.device)
     _check(lib().rn_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)), "rn_sweep")
+
+
+def sweep_kernel_kind(net: Network, n_traj, precision="fp64"):
+    """``rn_sweep_kernel_kind``: "network" when rn_sweep runs a kernel compiled
+    for this network (compiling it now if needed), "generic" otherwise."""
+    if precision not in PRECISIONS:
+        raise ValueError("precision must be 'fp64' or 'fp32'")
+    rc = lib().rn_sweep_kernel_kind(net.handle, PRECISIONS[precision], int(n_traj))
+    if rc < 0:
+        raise RNError(rc, "rn_sweep_kernel_kind")
+    return "network" if rc == 1 else "generic"
 
 
 def validate_times(times):

@@ -228,3 +228,26 @@ def test_empty_sweep_is_a_noop():
     rn.sweep(net, r, x, tm, o, s, seed=1)
     torch.cuda.synchronize()
     assert int(o.item()) == -7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_network_compiled_kernel_matches_generic(monkeypatch, precision):
+    # the kernel compiled for one network and the generic kernel evaluate the
+    # same operations in the same order: identical trajectories in either
+    # precision (the 50x100 network, 300 trajectories with a ragged last wave)
+    w = gen.synthetic_workload(n_traj=300)
+    net = rn.Network(w.net)
+    _say(f"case network-compiled vs generic {precision}")
+    assert rn.sweep_kernel_kind(net, w.n_traj, precision) == "network"
+    a, sa = rn.run(net, w.rates, w.x0, w.times, seed=21, precision=precision)
+    monkeypatch.setenv("RN_JIT", "0")
+    assert rn.sweep_kernel_kind(net, w.n_traj, precision) == "generic"
+    b, sb = rn.run(net, w.rates, w.x0, w.times, seed=21, precision=precision)
+    same = np.all(a == b, axis=(0, 1)) & np.all(sa == sb, axis=1)
+    _say(f"  {same.sum()}/{same.size} identical")
+    assert same.all()
+
+
+def test_large_network_uses_generic_kernel():
+    net = rn.Network(gen.random_network(3001, 250, 500))
+    assert rn.sweep_kernel_kind(net, 96) == "generic"

@@ -31,16 +31,18 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_kernel_synthetic_50x100_fp64_traffic.json")
 
 
-def measured_traffic():
+def measured_traffic(kind):
     """HBM bytes per launch of the FP64 sweep kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE record (each counter scaled by what it
-    reads for a copy of known size), or None when the kernel sources changed
-    since the counters were taken."""
+    reads for a copy of known size), or None when the record is for the other
+    kernel kind or the kernel sources changed since the counters were taken."""
     import hashlib
 
     try:
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
+        return None
+    if rec.get("kind") != kind:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -87,15 +89,177 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
+    ap.add_argument("--workload", choices=("synthetic", "batch", "serve"), default="synthetic",
+                    help="synthetic: the 50x100 sweep of 65,536 trajectories (the headline); "
+                         "batch: the uneven batch of 64 networks, batched vs one sweep at a "
+                         "time; serve: a Poisson stream of sweep jobs through rn_server")
+    ap.add_argument("--batch-networks", type=int, default=64)
+    ap.add_argument("--serve-jobs", type=int, default=1050)
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
+    ap.add_argument("--serve-warmup", type=int, default=50, help="jobs left out of latencies")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="scale of trajectories and t_end per job (1 = the stated stream)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
     return ap.parse_args()
+
+
+def serve_main(args, torch, gen, rn):
+    """Serving stream: jobs arrive as a Poisson process (--serve-rate per second),
+    each a seeded network of 20-300 reactions with 1,024-65,536 trajectories and
+    t_end logU[10, 500] (both times --serve-scale), 101 samples; they go through
+    rn_server with a fixed HBM budget and a few stream slots.  Latency = time
+    from arrival to results on the host; the first --serve-warmup jobs are left
+    out.  value = trajectory-steps of the measured jobs / their wall span."""
+    arrivals, specs = gen.serve_specs(n_jobs=args.serve_jobs, rate=args.serve_rate,
+                                      t_scale=args.serve_scale, t_end_scale=args.serve_scale)
+    ws = specs  # one entry per job; workloads are built at submission
+    nets = {}
+    srv = rn.Server(int(args.serve_budget_gib * 2**30), max_running=args.serve_streams)
+    kw = dict(precision=args.precision)
+    done_at, steps, start = {}, {}, None
+    next_job, ids = 0, {}
+    t0 = time.perf_counter()
+    last_print = t0
+    while len(done_at) < len(ws):
+        now = time.perf_counter() - t0
+        while next_job < len(ws) and arrivals[next_job] <= now:
+            w = gen.serve_job(specs[next_job])
+            nets[next_job] = rn.Network(w.net)
+            ids[srv.submit(nets[next_job], w.rates, w.x0, w.times, seed=w.seed, **kw)] = next_job
+            next_job += 1
+        for jid in srv.poll():
+            k = ids.pop(jid)
+            _, st = srv.fetch(jid)
+            del nets[k]
+            done_at[k] = time.perf_counter() - t0
+            steps[k] = int(st[:, 0].sum() + st[:, 1].sum())
+        if time.perf_counter() - last_print > 10:
+            last_print = time.perf_counter()
+            print(f"[bench] serve t={now:.0f}s submitted {next_job} done {len(done_at)} "
+                  f"{srv.status()}", file=sys.stderr, flush=True)
+        if next_job < len(ws) and not ids:
+            time.sleep(max(0.0, min(arrivals[next_job] - now, 0.01)))
+        else:
+            time.sleep(0.0005)
+    srv.close()
+    meas = range(min(args.serve_warmup, len(ws) - 1), len(ws))
+    lat = np.array([done_at[k] - arrivals[k] for k in meas])
+    span = max(done_at[k] for k in meas) - min(arrivals[k] for k in meas)
+    tot = sum(steps[k] for k in meas)
+    offered = args.serve_rate
+    achieved = len(meas) / span
+    result = {
+        "metric": "serving: trajectory-steps/sec and p50/p99 sweep-job latency (1 GPU)",
+        "value": tot / span, "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": len(meas), "warmup": len(ws) - len(meas), "ms_per_step": 1e3 * span / len(meas),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": "Poisson stream of sweep jobs", "jobs": len(ws),
+                   "rate_per_s": offered, "scale": args.serve_scale,
+                   "budget_gib": args.serve_budget_gib, "streams": args.serve_streams},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3,
+                       "p99": float(np.percentile(lat, 99)) * 1e3},
+        "jobs_per_s": {"offered": offered, "completed": achieved},
+        "overloaded": bool(achieved < 0.95 * offered),
+    }
+    print(json.dumps(result), flush=True)
+
+
+def batch_main(args, torch, gen, rn):
+    """Uneven batch: 64 seeded networks of 10-500 reactions (species = reactions/2)
+    with 256-16,384 trajectories each, t_end 50, 200 samples.  Times the whole
+    batch as one rn_batch graph launch and as one rn_sweep per network in turn;
+    value = trajectory-steps of the batch / wall time of the graph launch."""
+    dev = torch.device("cuda:0")
+    ws = gen.batch_workloads(n_networks=args.batch_networks)
+    jobs = []
+    for k, w in enumerate(ws):
+        S, N, T = len(w.times), w.net.n_species, w.n_traj
+        jobs.append(dict(net=rn.Network(w.net), seed=w.seed, T=T,
+                         rates=torch.from_numpy(w.rates).to(dev),
+                         x0=torch.from_numpy(w.x0).to(dev),
+                         times=torch.from_numpy(w.times).to(dev),
+                         out=torch.empty((S, N, T), dtype=torch.int32, device=dev),
+                         stats=torch.empty((T, 4), dtype=torch.int64, device=dev)))
+    t0 = time.perf_counter()
+    from concurrent.futures import ThreadPoolExecutor, as_completed
+    kinds = [None] * len(jobs)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        futs = {ex.submit(rn.sweep_kernel_kind, j["net"], j["T"], args.precision): k
+                for k, j in enumerate(jobs)}
+        for n_done, f in enumerate(as_completed(futs), 1):
+            kinds[futs[f]] = f.result()
+            print(f"[bench] kernels ready {n_done}/{len(jobs)} "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] batch of {len(jobs)}: {kinds.count('network')} network-compiled, "
+          f"{kinds.count('generic')} generic kernels; setup {setup_s:.1f} s",
+          file=sys.stderr, flush=True)
+    kw = dict(precision=args.precision)
+
+    def sequential(report=False):
+        for k, j in enumerate(jobs):
+            rn.sweep(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
+                     seed=j["seed"], **kw)
+            if report:
+                torch.cuda.synchronize()
+                print(f"[bench] job {k + 1}/{len(jobs)} done (M={j['net'].n_reactions}, "
+                      f"T={j['T']})", file=sys.stderr, flush=True)
+
+    batch = rn.Batch()
+    for j in jobs:
+        batch.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
+                  seed=j["seed"], **kw)
+    # warm-up: every job once, one at a time (reporting progress), then the graph
+    t = time.perf_counter()
+    sequential(report=True)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t  # one at a time, FIFO
+    batch.launch()
+    torch.cuda.synchronize()
+    print("[bench] graph recorded", file=sys.stderr, flush=True)
+    bat = []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        batch.launch()
+        torch.cuda.synchronize()
+        bat.append(time.perf_counter() - t)
+        print(f"[bench] batch launch {i + 1}/{args.steps}: {bat[-1] * 1e3:.0f} ms",
+              file=sys.stderr, flush=True)
+    bat_s = float(np.mean(bat))
+    steps = sum(int(st[:, 0].sum() + st[:, 1].sum()) for st in
+                (j["stats"].cpu().numpy().view(np.uint64) for j in jobs))
+    print(f"[bench] batch {bat_s * 1e3:.1f} ms, one at a time {seq_s * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    result = {
+        "metric": "trajectory-steps/sec, uneven batch of 64 networks (1 GPU)",
+        "value": steps / bat_s, "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": bat_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"uneven batch of {len(jobs)} synthetic networks, "
+                               f"{args.precision.upper()}", "n_networks": len(jobs),
+                   "n_traj_total": int(sum(j["T"] for j in jobs)),
+                   "reactions": [int(j["net"].n_reactions) for j in jobs],
+                   "steps_per_batch": steps},
+        "kernels": {"network": kinds.count("network"), "generic": kinds.count("generic")},
+        "setup_s": {"kernel_compile": setup_s},
+        "one_at_a_time": {"value": steps / seq_s, "ms_per_step": seq_s * 1e3},
+        "speedup_vs_one_at_a_time": seq_s / bat_s,
+    }
+    batch.close()
+    print(json.dumps(result), flush=True)
 
 
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs each sweep on a single "
-              "MI355X (trajectories shard with zero exchange; see the design notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: each sweep runs on a single MI355X "
+              "(trajectories shard across GPUs with no exchange, so more GPUs add "
+              "throughput by splitting the trajectory range).  Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -104,6 +268,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batch":
+        batch_main(args, torch, gen, rn)
+        return
+    if args.workload == "serve":
+        serve_main(args, torch, gen, rn)
+        return
     dev = torch.device("cuda:0")
     w = gen.synthetic_workload(n_traj=args.n_traj)
     T, M, N, S = w.n_traj, w.net.n_reactions, w.net.n_species, len(w.times)
@@ -115,6 +285,16 @@ def main():
     stats = torch.empty((T, 4), dtype=torch.int64, device=dev)
     kw = dict(seed=w.seed, eps=w.eps, n_c=w.n_c, precision=args.precision)
     print(f"[bench] workload {w.name}: T={T} N={N} M={M} S={S}", file=sys.stderr, flush=True)
+    # Setup, outside every timed step: the library compiles the kernel for this
+    # network on first use (hipRTC); do it here and report its cost apart.
+    t0 = time.perf_counter()
+    kind = rn.sweep_kernel_kind(net, T, args.precision)
+    setup_s = time.perf_counter() - t0
+    real = "double" if args.precision == "fp64" else "float"
+    wg = 256 if T >= 256 * torch.cuda.get_device_properties(dev).multi_processor_count else 64
+    kernel = (f"rn_net_sweep<{wg}, {real}> (compiled for the network)" if kind == "network"
+              else f"sweep_kernel<{wg}, {rate_segments(M)}, {real}>")
+    print(f"[bench] kernel {kernel}; setup {setup_s:.1f} s", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         rn.sweep(net, rates, x0, times, out, stats, **kw)
@@ -166,6 +346,8 @@ def main():
                    "steps_per_sweep": steps_per_sweep,
                    "leaps": int(st2[:, 0].sum()), "ssa_events": int(st2[:, 1].sum()),
                    "rejections": int(st2[:, 2].sum())},
+        "kernel": kernel,
+        "setup_s": {"kernel_compile": setup_s},
         "latency_ms": {"p50": float(np.percentile(kern_ms, 50)),
                        "p99": float(np.percentile(kern_ms, 99))},
     }
@@ -196,8 +378,8 @@ def main():
         result["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                               "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                               "frac": achieved / PEAK_LANE_OPS,
-                              "traffic": measured_traffic() if T == 65536 else None,
-                              "kernel": f"sweep_kernel<256, {rate_segments(M)}, double>",
+                              "traffic": measured_traffic(kind) if T == 65536 else None,
+                              "kernel": kernel,
                               "ops_per_step": ops_per_step,
                               "kernel_ms": float(np.mean(kern_ms))}
     else:

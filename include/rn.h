@@ -184,6 +184,79 @@ int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream)
 int rn_sweep_kernel_kind(const rn_network *net, int32_t precision, int64_t n_traj);
 
 /*
+ * Batched sweeps: many jobs (each a network handle and an rn_sweep_args, e.g. a
+ * set of networks of uneven size and trajectory count) launched together.  The
+ * jobs are independent parameter sweeps (paper, Aims and motivation section);
+ * the first rn_batch_launch records all of them into one HIP graph as parallel
+ * branches (largest jobs first, spread over a few internal streams), and every
+ * later launch replays that graph with one hipGraphLaunch on `hip_stream`.
+ * Each job's results are exactly those of rn_sweep with the same arguments.
+ *
+ *  rn_batch_add   validates `args` like rn_sweep (and compiles the network's
+ *                 kernel if needed), copies them; the buffers they point to
+ *                 and the network handle must stay valid while the batch is
+ *                 used.  Jobs cannot be added after the first launch
+ *                 (RN_E_INVALID_ARG).  All jobs must be on one device.
+ *  rn_batch_launch  asynchronous on `hip_stream`; a replay reads the inputs
+ *                 and rewrites the outputs the buffers hold at that time.
+ *  rn_batch_size  number of non-empty jobs, or RN_E_INVALID_ARG.
+ * Errors: RN_E_INVALID_ARG, RN_E_NOMEM, RN_E_DEVICE, and those of rn_sweep.
+ */
+typedef struct rn_batch rn_batch;
+int rn_batch_create(rn_batch **out);
+int rn_batch_add(rn_batch *b, const rn_network *net, const rn_sweep_args *args);
+int rn_batch_size(const rn_batch *b);
+int rn_batch_launch(rn_batch *b, void *hip_stream);
+void rn_batch_free(rn_batch *b);
+
+/*
+ * Sweep-job server: jobs of different networks and sizes admitted continuously
+ * into a fixed HBM budget (many parameter sweeps in flight at once: paper, Aims
+ * and motivation section).  rn_server_create allocates the budget once as an
+ * arena; each job holds one block of it (inputs, samples, stats) from admission
+ * until its results are fetched.  Jobs are admitted in submission order as soon
+ * as a block and one of `max_running` stream slots are free, so jobs submitted
+ * while others run overlap on the device.  Work advances inside the calls
+ * (there is no server thread): call rn_server_poll regularly.  A job uses its
+ * network's compiled kernel when the process already has it and the generic
+ * kernel otherwise (same results), starting the compilation in the background.
+ * Each job's results equal those of rn_sweep with the same inputs and options.
+ *
+ *  rn_serve_job   host inputs, copied at submission (the caller may free them
+ *                 on return); `params` supplies seed, eps, n_c, ssa_factor,
+ *                 ssa_burst, max_steps, method, precision and cle_threshold (its
+ *                 pointer, size and stride fields are ignored).  The network
+ *                 handle must stay valid until the job is fetched.
+ *  rn_server_submit   queues the job and returns its id; RN_E_NOMEM if the job
+ *                 alone exceeds the budget, RN_E_INVALID_ARG for bad inputs.
+ *  rn_server_poll     admits and launches what fits, then reports up to
+ *                 max_ids finished job ids (each once).
+ *  rn_server_fetch    copies a finished (or running: it waits) job's samples
+ *                 [n_times][N][n_traj] and stats [n_traj][4] to host buffers
+ *                 (either may be null) and releases its memory;
+ *                 RN_E_INVALID_ARG for an unknown or still-queued job.
+ *  rn_server_status   queued and running job counts, bytes of the budget held.
+ *  rn_server_free     waits for running jobs and releases everything.
+ */
+typedef struct rn_server rn_server;
+typedef struct {
+  const rn_network *net;
+  int64_t n_traj;
+  const double *rates; /* host, [M][n_traj] */
+  const int32_t *x0;   /* host, [N], or [N][n_traj] when x0_per_traj != 0 */
+  int32_t x0_per_traj;
+  const double *times; /* host, [n_times]: finite, >= 0, strictly increasing */
+  int32_t n_times;
+  rn_sweep_args params;
+} rn_serve_job;
+int rn_server_create(int64_t hbm_budget_bytes, int32_t max_running, rn_server **out);
+int rn_server_submit(rn_server *s, const rn_serve_job *job, int64_t *job_id);
+int rn_server_poll(rn_server *s, int64_t *done_ids, int32_t max_ids, int32_t *n_done);
+int rn_server_fetch(rn_server *s, int64_t job_id, int32_t *out, uint64_t *stats);
+int rn_server_status(rn_server *s, int64_t *queued, int64_t *running, int64_t *bytes_in_use);
+void rn_server_free(rn_server *s);
+
+/*
  * Deterministic sweep: the reaction-rate equations that abundant species follow
  * (paper, Methods section: mean-field ODEs, which agree with the stochastic
  * model in the thermodynamic limit),

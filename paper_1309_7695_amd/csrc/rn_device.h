@@ -129,8 +129,9 @@ __device__ __forceinline__ double log_factorial(double kf, const double* table) 
 
 // Poisson(lam) for lam >= 10: Hoermann's transformed rejection with squeeze
 // (PTRS, Insurance: Math. & Econ. 12 (1993) 39); round r draws its (U, V) pair
-// from its own Philox block.
-__device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_t n, uint32_t j,
+// from its own Philox block.  The body is inlined where a kernel has one call
+// site; the out-of-line copy below serves kernels with many.
+__device__ __forceinline__ uint32_t ptrs_body(double lam, uint32_t traj, uint32_t n, uint32_t j,
                                               uint32_t k0, uint32_t k1, const double* lfact) {
   const double smu = sqrt(lam);
   const double b = 0.931 + 2.53 * smu;
@@ -154,6 +155,11 @@ __device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_
   return clamp_draw(floor(lam));
 }
 
+__device__ __noinline__ uint32_t poisson_ptrs(double lam, uint32_t traj, uint32_t n, uint32_t j,
+                                              uint32_t k0, uint32_t k1, const double* lfact) {
+  return ptrs_body(lam, traj, n, j, k0, k1, lfact);
+}
+
 // Chemical Langevin increment for mean lam: round(lam + sqrt(lam) z), z standard
 // normal by Box-Muller, (u1, u2) from the reaction's first PTRS block; floored
 // at 0 and clamped like every draw.
@@ -168,7 +174,8 @@ __device__ __noinline__ uint32_t cle_count(double lam, uint32_t traj, uint32_t n
   return clamp_draw(kf);
 }
 
-template <typename R>
+// kInline: the PTRS body is inlined (one call site per kernel) instead of called.
+template <typename R, bool kInline = false>
 __device__ __forceinline__ uint32_t poisson(R lam, uint32_t hi, uint32_t lo, uint32_t traj,
                                             uint32_t n, uint32_t j, uint32_t k0, uint32_t k1,
                                             const double* lfact, double cle) {
@@ -176,7 +183,8 @@ __device__ __forceinline__ uint32_t poisson(R lam, uint32_t hi, uint32_t lo, uin
   if (lam < R(10)) return poisson_inversion<R>(lam, Real<R>::uni(hi, lo));
   const double ld = (double)lam;
   if (cle > 0.0 && ld >= cle) return cle_count(ld, traj, n, j, k0, k1);
-  return poisson_ptrs(ld, traj, n, j, k0, k1, lfact);
+  if constexpr (kInline) return ptrs_body(ld, traj, n, j, k0, k1, lfact);
+  else return poisson_ptrs(ld, traj, n, j, k0, k1, lfact);
 }
 
 // Mass-action combinatorial factor h = A * B (halved for a homodimer, where

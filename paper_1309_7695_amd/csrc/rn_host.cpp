@@ -19,6 +19,7 @@
 #include "rn.h"
 #include "rn_jit.h"
 #include "rn_kernel.h"
+#include "rn_plan.h"
 
 struct rn_network {
   int32_t N = 0, M = 0;
@@ -347,14 +348,24 @@ void rn_free_network(rn_network* net) {
   delete net;
 }
 
+}  // extern "C"
+
 // The network-compiled kernel for this handle, precision and workgroup size
 // (compiled on first use), or null when the generic kernels run.
-static hipFunction_t network_kernel(const rn_network* net, int32_t precision, int wg) {
+// wait = false: use it only if already compiled (else start compiling it in the
+// background and run the generic kernel this time).
+static hipFunction_t network_kernel(const rn_network* net, int32_t precision, int wg,
+                                    bool wait = true) {
   if (net->jit_consts.empty() || !rn::jit_enabled()) return nullptr;
-  return rn::jit_kernel(net->jit_consts, precision == RN_FP32 ? rn::kJitFP32 : rn::kJitFP64, wg);
+  const int prec = precision == RN_FP32 ? rn::kJitFP32 : rn::kJitFP64;
+  return wait ? rn::jit_kernel(net->jit_consts, prec, wg)
+              : rn::jit_kernel_nowait(net->jit_consts, prec, wg);
 }
 
-int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
+namespace rn_internal {
+
+int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
+               bool wait_compile) {
   if (!net || !a) return RN_E_INVALID_ARG;
   if (a->n_traj < 0 || a->traj_offset < 0 || a->traj_offset + a->n_traj > (int64_t)1 << 32)
     return RN_E_INVALID_ARG;
@@ -367,7 +378,12 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   if (a->precision != RN_FP64 && a->precision != RN_FP32) return RN_E_INVALID_ARG;
   if (!(a->cle_threshold == 0.0 || (a->cle_threshold >= 10.0 && a->cle_threshold <= 1e300)))
     return RN_E_INVALID_ARG;
-  if (a->n_traj == 0) return RN_OK;
+  plan = SweepPlan{};
+  plan.precision = a->precision;
+  if (a->n_traj == 0) {
+    plan.empty = true;
+    return RN_OK;
+  }
   if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats) return RN_E_INVALID_ARG;
   if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj) return RN_E_INVALID_ARG;
   if (a->x0_ld != 0 && a->x0_ld < a->n_traj) return RN_E_INVALID_ARG;
@@ -384,7 +400,7 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
 
   const size_t per_lane =
       rn::lds_words_per_lane(net->N, padded_reactions(net->M)) * sizeof(int32_t);
-  rn::LaunchCfg cfg{};
+  rn::LaunchCfg& cfg = plan.cfg;
   cfg.rate_segs = net->M <= 16 * rn::kMaxRateSegs ? padded_reactions(net->M) / 16 : 0;
   // 256 lanes per workgroup (one wave per SIMD of a CU) when the sweep fills the
   // chip; otherwise single-wave workgroups spread over more CUs.
@@ -393,7 +409,7 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   cfg.lds_bytes = per_lane * cfg.wg;
   if (cfg.lds_bytes > (size_t)max_lds) return RN_E_UNSUPPORTED;
 
-  rn::SweepParams p{};
+  rn::SweepParams& p = plan.p;
   p.net = net->dev;
   p.rates = a->rates;
   p.rates_ld = a->rates_ld;
@@ -416,16 +432,33 @@ int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
   p.method = a->method;
   p.cle_threshold = a->cle_threshold;
   p.theta = sched_theta();
-  const int jwg = a->n_traj >= (int64_t)256 * n_cu ? 256 : 64;
-  if (hipFunction_t fn = network_kernel(net, a->precision, jwg)) {
-    e = rn::jit_launch(fn, p, jwg, rn::jit_lds_bytes(net->N, net->M, jwg),
-                       (hipStream_t)hip_stream);
-  } else {
-    e = a->precision == RN_FP32 ? rn::launch_sweep_f32(p, cfg, (hipStream_t)hip_stream)
-                                : rn::launch_sweep_f64(p, cfg, (hipStream_t)hip_stream);
+  plan.wg = a->n_traj >= (int64_t)256 * n_cu ? 256 : 64;
+  plan.fn = network_kernel(net, a->precision, plan.wg, wait_compile);
+  if (plan.fn) {
+    plan.lds = rn::jit_lds_bytes(net->N, net->M, plan.wg);
+    if (plan.lds > (size_t)max_lds) plan.fn = nullptr;
   }
-  if (e != hipSuccess) return device_error(e);
   return RN_OK;
+}
+
+hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
+  if (plan.empty) return hipSuccess;
+  if (plan.fn) return rn::jit_launch(plan.fn, plan.p, plan.wg, plan.lds, stream);
+  return plan.precision == RN_FP32 ? rn::launch_sweep_f32(plan.p, plan.cfg, stream)
+                                   : rn::launch_sweep_f64(plan.p, plan.cfg, stream);
+}
+
+int device_status(hipError_t e) { return e == hipSuccess ? RN_OK : device_error(e); }
+
+}  // namespace rn_internal
+
+extern "C" {
+
+int rn_sweep(const rn_network* net, const rn_sweep_args* a, void* hip_stream) {
+  rn_internal::SweepPlan plan;
+  const int rc = rn_internal::plan_sweep(net, a, plan);
+  if (rc != RN_OK) return rc;
+  return rn_internal::device_status(rn_internal::launch_plan(plan, (hipStream_t)hip_stream));
 }
 
 int rn_sweep_kernel_kind(const rn_network* net, int32_t precision, int64_t n_traj) {

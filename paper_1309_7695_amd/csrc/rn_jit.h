@@ -27,6 +27,9 @@ bool jit_enabled();
 // The compiled kernel for a network prelude, compiled on first use; null when
 // hipRTC is unavailable or the compilation fails.
 hipFunction_t jit_kernel(const std::string& consts, int precision, int wg);
+// The compiled kernel if it is ready now; otherwise null, after starting its
+// compilation on a background thread (so a later call finds it).
+hipFunction_t jit_kernel_nowait(const std::string& consts, int precision, int wg);
 hipError_t jit_launch(hipFunction_t fn, const SweepParams& p, int wg, size_t lds,
                       hipStream_t stream);
 

@@ -48,8 +48,9 @@ __device__ __forceinline__ void sfor(F&& f) {
 
 // An empty asm that claims to change v (and emits nothing).
 __device__ __forceinline__ void opaque(int32_t& v) { asm volatile("" : "+v"(v)); }
-template <int... I>
-__device__ __forceinline__ void opaque_all_(int32_t* x, ISeq<int, I...>*) {
+__device__ __forceinline__ void opaque(uint32_t& v) { asm volatile("" : "+v"(v)); }
+template <typename T, int... I>
+__device__ __forceinline__ void opaque_all_(T* x, ISeq<int, I...>*) {
   (opaque(x[I]), ...);
 }
 
@@ -152,11 +153,15 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
     else return (R)x[ia] * (R)x[ib];
   };
   auto aj = [&](auto jc) -> R { return c.get(decltype(jc)::value) * hj(jc); };
-  // An empty asm that claims to change every count: placed at the start of
-  // each phase, it keeps the compiler from carrying propensities from one phase
-  // into the next (or computing a whole leap's means at once), which would hold
-  // hundreds of values in registers and spill them.
-  auto fence = [&]() { opaque_all_(x, (__make_integer_seq<ISeq, int, N>*)nullptr); };
+  // An empty asm that claims to change every count and critical-bit word:
+  // placed at the start of each phase, it keeps the compiler from carrying
+  // propensities or per-reaction critical tests from one phase into the next
+  // (or computing a whole leap's means at once), which would hold hundreds of
+  // values in registers and spill them.
+  auto fence = [&]() {
+    opaque_all_(x, (__make_integer_seq<ISeq, int, N>*)nullptr);
+    opaque_all_(crit, (__make_integer_seq<ISeq, int, CW>*)nullptr);
+  };
   auto critbit = [&](auto jc) -> bool {
     constexpr int j = decltype(jc)::value;
     return (crit[j >> 5] >> (j & 31)) & 1u;
@@ -394,18 +399,24 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
             }
           });
           I16 kv;
+          // one reaction per iteration, so the samplers (PTRS inlined) have a
+          // single copy per block; the pair's Philox block is made at even e
+          Words w = {0u, 0u, 0u, 0u};
 #pragma unroll 1
-          for (int e = 0; e < 16; e += 2) {
+          for (int e = 0; e < 16; ++e) {
             const int je = base + e;
             if (je >= M) break;
-            const R le = lam[e], lo = lam[e + 1];
-            Words w = {0u, 0u, 0u, 0u};
-            if ((le > R(0) && le < R(10)) || (lo > R(0) && lo < R(10)))
-              w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
-            kv[e] = (int32_t)poisson<R>(le, w.w0, w.w1, traj, n, (uint32_t)je, k0, k1,
-                                        p.net.log_fact, p.cle_threshold);
-            kv[e + 1] = (int32_t)poisson<R>(lo, w.w2, w.w3, traj, n, (uint32_t)(je + 1), k0, k1,
-                                            p.net.log_fact, p.cle_threshold);
+            const R le = lam[e];
+            if ((e & 1) == 0) {
+              const R lo = lam[e + 1];
+              w = {0u, 0u, 0u, 0u};
+              if ((le > R(0) && le < R(10)) || (lo > R(0) && lo < R(10)))
+                w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
+            }
+            const uint32_t hi = (e & 1) ? w.w2 : w.w0;
+            const uint32_t lw = (e & 1) ? w.w3 : w.w1;
+            kv[e] = (int32_t)poisson<R, true>(le, hi, lw, traj, n, (uint32_t)je, k0, k1,
+                                              p.net.log_fact, p.cle_threshold);
           }
           sfor<0, 16>([&](auto ec) {
             constexpr int e = decltype(ec)::value, j = base + e;

@@ -1,0 +1,30 @@
+// rn_plan.h -- internal: a validated sweep ready to launch, shared by rn_sweep
+// and the batched launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "rn.h"
+#include "rn_kernel.h"
+
+namespace rn_internal {
+
+struct SweepPlan {
+  bool empty = false;          // n_traj == 0: nothing to launch
+  int32_t precision = RN_FP64;
+  hipFunction_t fn = nullptr;  // network-compiled kernel, or null for the generic one
+  int wg = 0;                  // workgroup size of the network-compiled kernel
+  size_t lds = 0;              // its dynamic LDS bytes
+  rn::LaunchCfg cfg{};         // generic kernel configuration
+  rn::SweepParams p{};
+};
+
+// Validate the arguments and choose the kernel.  wait_compile: compile the
+// network's kernel now if needed; otherwise use it only when already compiled
+// (starting its compilation in the background).  Returns RN_OK or RN_E_*.
+int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
+               bool wait_compile = true);
+hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream);
+// RN_OK for hipSuccess, else RN_E_DEVICE (recording the HIP code).
+int device_status(hipError_t e);
+
+}  // namespace rn_internal

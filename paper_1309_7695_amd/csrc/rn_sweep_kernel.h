@@ -519,9 +519,6 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
 
 template <int WG, int NSEG, typename R>
 hipError_t launch_one(const SweepParams& p, size_t lds, hipStream_t stream, int64_t blocks) {
-  hipError_t err = hipFuncSetAttribute((const void*)sweep_kernel<WG, NSEG, R>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (err != hipSuccess) return err;
   hipLaunchKernelGGL((sweep_kernel<WG, NSEG, R>), dim3((unsigned)blocks), dim3(WG), lds, stream,
                      p);
   return hipGetLastError();

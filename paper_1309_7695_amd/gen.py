@@ -261,6 +261,61 @@ def stiff_workload(n_traj=65536, seed=4):
                               low_count_frac=0.2)
 
 
+def int_log_uniform(rng, lo, hi, size=None):
+    """Integers round(10^U(log10 lo, log10 hi)), clipped to [lo, hi]."""
+    return np.clip(np.rint(log_uniform(rng, lo, hi, size)), lo, hi).astype(np.int64)
+
+
+def batch_workloads(n_networks=64, seed=3000, m_range=(10, 500), t_range=(256, 16384),
+                    t_end=50.0, n_samples=200, t_scale=1.0):
+    """Uneven batch: network k from seed + k with M ~ integer logU[m_range] reactions
+    and N = M // 2 species (same mix and rate/count distributions as the
+    50x100 network), T_k ~ integer logU[t_range] trajectories (times t_scale,
+    at least 1).  Sizes are drawn from a generator seeded with ``seed``."""
+    rng = np.random.default_rng(seed)
+    ms = int_log_uniform(rng, m_range[0], m_range[1], n_networks)
+    ts = int_log_uniform(rng, t_range[0], t_range[1], n_networks)
+    out = []
+    for k in range(n_networks):
+        m = int(ms[k])
+        n_traj = max(1, int(round(ts[k] * t_scale)))
+        w = synthetic_workload(n_traj=n_traj, seed=seed + k, n_species=max(m // 2, 1),
+                               n_reactions=m, t_end=t_end, n_samples=n_samples)
+        out.append(w)
+    return out
+
+
+def serve_specs(n_jobs=1050, seed=5000, rate=50.0, m_range=(20, 300), t_range=(1024, 65536),
+                t_end_range=(10.0, 500.0), n_samples=101, t_scale=1.0, t_end_scale=1.0):
+    """Serving stream: arrival times of a Poisson process of `rate` jobs/s
+    (generator seed 5) and, per job k, (seed + k, M, T, t_end, n_samples) with
+    M ~ integer logU[m_range] reactions, T ~ integer logU[t_range] trajectories
+    (times t_scale) and t_end ~ logU[t_end_range] (times t_end_scale)."""
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_jobs))
+    srng = np.random.default_rng(seed)
+    ms = int_log_uniform(srng, m_range[0], m_range[1], n_jobs)
+    ts = int_log_uniform(srng, t_range[0], t_range[1], n_jobs)
+    ends = log_uniform(srng, t_end_range[0], t_end_range[1], n_jobs)
+    specs = [(seed + k, int(ms[k]), max(1, int(round(ts[k] * t_scale))),
+              float(ends[k]) * t_end_scale, n_samples) for k in range(n_jobs)]
+    return arrivals, specs
+
+
+def serve_job(spec):
+    """The workload of one serving-stream spec: the network of its seed with
+    N = M // 2 species (mix and distributions of the 50x100 network)."""
+    seed, m, n_traj, t_end, n_samples = spec
+    return synthetic_workload(n_traj=n_traj, seed=seed, n_species=max(m // 2, 1),
+                              n_reactions=m, t_end=t_end, n_samples=n_samples)
+
+
+def serve_jobs(n_jobs=1050, **kw):
+    """(arrival times, workloads) of the serving stream, built eagerly."""
+    arrivals, specs = serve_specs(n_jobs=n_jobs, **kw)
+    return arrivals, [serve_job(sp) for sp in specs]
+
+
 def workload(name, n_traj=None):
     if name in ("enzyme", "enzyme_4x3"):
         return enzyme_workload(n_traj or 1024)

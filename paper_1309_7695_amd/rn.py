@@ -28,6 +28,9 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
            "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_sweep_kernel_kind",
+           "rn_batch_create", "rn_batch_add", "rn_batch_size", "rn_batch_launch", "rn_batch_free",
+           "rn_server_create", "rn_server_submit", "rn_server_poll", "rn_server_fetch",
+           "rn_server_status", "rn_server_free",
            "rn_moments", "rn_ode_args_init",
            "rn_ode_work_doubles", "rn_ode_sweep", "rn_strerror", "rn_last_device_error"]
 
@@ -49,6 +52,12 @@ class SweepArgs(C.Structure):
                 ("eps", C.c_double), ("n_c", C.c_int32), ("ssa_factor", C.c_double),
                 ("ssa_burst", C.c_int32), ("max_steps", C.c_uint64),
                 ("method", C.c_int32), ("precision", C.c_int32), ("cle_threshold", C.c_double)]
+
+
+class ServeJob(C.Structure):
+    _fields_ = [("net", C.c_void_p), ("n_traj", C.c_int64), ("rates", C.c_void_p),
+                ("x0", C.c_void_p), ("x0_per_traj", C.c_int32), ("times", C.c_void_p),
+                ("n_times", C.c_int32), ("params", SweepArgs)]
 
 
 class OdeArgs(C.Structure):
@@ -95,6 +104,29 @@ def lib():
         L.rn_sweep.restype = C.c_int
         L.rn_sweep_kernel_kind.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
         L.rn_sweep_kernel_kind.restype = C.c_int
+        L.rn_batch_create.argtypes = [C.POINTER(C.c_void_p)]
+        L.rn_batch_create.restype = C.c_int
+        L.rn_batch_add.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SweepArgs)]
+        L.rn_batch_add.restype = C.c_int
+        L.rn_batch_size.argtypes = [C.c_void_p]
+        L.rn_batch_size.restype = C.c_int
+        L.rn_batch_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.rn_batch_launch.restype = C.c_int
+        L.rn_batch_free.argtypes = [C.c_void_p]
+        L.rn_batch_free.restype = None
+        L.rn_server_create.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_void_p)]
+        L.rn_server_create.restype = C.c_int
+        L.rn_server_submit.argtypes = [C.c_void_p, C.POINTER(ServeJob), C.POINTER(C.c_int64)]
+        L.rn_server_submit.restype = C.c_int
+        L.rn_server_poll.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+        L.rn_server_poll.restype = C.c_int
+        L.rn_server_fetch.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.rn_server_fetch.restype = C.c_int
+        L.rn_server_status.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64)]
+        L.rn_server_status.restype = C.c_int
+        L.rn_server_free.argtypes = [C.c_void_p]
+        L.rn_server_free.restype = None
         L.rn_moments.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int64,
                                  C.c_void_p, C.c_void_p, C.c_void_p]
         L.rn_moments.restype = C.c_int
@@ -168,16 +200,16 @@ class Network:
             pass
 
 
-def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
-          n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
-          cle_threshold=0.0, precision="fp64", stream=None):
-    """Enqueue ``rn_sweep`` on ``stream`` (default: torch's current stream).
+def sweep_args(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
+               n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
+               cle_threshold=0.0, precision="fp64"):
+    """Check the tensors and marshal an ``rn_sweep_args`` for them.
 
     ``rates`` float64 [M][>=T] (row stride = ld), ``x0`` int32 [N] or [N][>=T],
     ``times`` float64 [S], ``out`` int32 [S][N][>=T] (last dim stride = ld),
     ``stats`` uint64/int64 [T][4]; all CUDA (HIP) tensors on the network's
     device.  T is taken from ``stats``.  ``precision`` is "fp64" or "fp32"
-    (RN_FP64 / RN_FP32).  Returns immediately."""
+    (RN_FP64 / RN_FP32)."""
     import torch
 
     if precision not in PRECISIONS:
@@ -225,9 +257,63 @@ def sweep(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, ep
     a.ssa_burst, a.max_steps, a.method, a.precision = int(ssa_burst), int(max_steps), \
         int(method), PRECISIONS[precision]
     a.cle_threshold = float(cle_threshold)
+    return a
+
+
+def sweep(net: Network, rates, x0, times, out, stats, *, stream=None, **kw):
+    """Enqueue ``rn_sweep`` on ``stream`` (default: torch's current stream); the
+    arguments are those of ``sweep_args``.  Returns immediately."""
+    import torch
+
+    a = sweep_args(net, rates, x0, times, out, stats, **kw)
     if stream is None:
         stream = torch.cuda.current_stream(rates.device)
     _check(lib().rn_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)), "rn_sweep")
+
+
+class Batch:
+    """``rn_batch``: sweep jobs launched together through one HIP graph.
+
+    ``add`` takes the arguments of ``sweep``; the batch keeps the tensors and
+    networks alive.  The first ``launch`` records the graph, later ones replay
+    it (rewriting the same output tensors)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().rn_batch_create(C.byref(h)), "rn_batch_create")
+        self.handle = h
+        self._keep = []
+
+    def add(self, net: Network, rates, x0, times, out, stats, **kw):
+        a = sweep_args(net, rates, x0, times, out, stats, **kw)
+        _check(lib().rn_batch_add(self.handle, net.handle, C.byref(a)), "rn_batch_add")
+        self._keep.append((net, rates, x0, times, out, stats))
+
+    def __len__(self):
+        n = lib().rn_batch_size(self.handle)
+        if n < 0:
+            raise RNError(n, "rn_batch_size")
+        return n
+
+    def launch(self, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().rn_batch_launch(self.handle, C.c_void_p(stream.cuda_stream)),
+               "rn_batch_launch")
+
+    def close(self):
+        if self.handle:
+            lib().rn_batch_free(self.handle)
+            self.handle = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sweep_kernel_kind(net: Network, n_traj, precision="fp64"):
@@ -239,6 +325,94 @@ def sweep_kernel_kind(net: Network, n_traj, precision="fp64"):
     if rc < 0:
         raise RNError(rc, "rn_sweep_kernel_kind")
     return "network" if rc == 1 else "generic"
+
+
+class Server:
+    """``rn_server``: sweep jobs admitted continuously into an HBM budget.
+
+    ``submit(net, rates, x0, times, seed=..., **options)`` takes host (numpy)
+    arrays and returns a job id; ``poll()`` advances the server and returns the
+    ids that finished; ``fetch(id)`` returns ``(out [S][N][T] int32, stats
+    [T][4] uint64)`` and frees the job's memory."""
+
+    def __init__(self, budget_bytes, max_running=4):
+        h = C.c_void_p()
+        _check(lib().rn_server_create(int(budget_bytes), int(max_running), C.byref(h)),
+               "rn_server_create")
+        self.handle = h
+        self._jobs = {}
+
+    def submit(self, net: Network, rates, x0, times, *, seed, eps=0.03, n_c=10,
+               ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
+               cle_threshold=0.0, precision="fp64"):
+        rates = np.ascontiguousarray(rates, dtype=np.float64)
+        x0 = np.ascontiguousarray(x0, dtype=np.int32)
+        times = validate_times(times)
+        M, T = rates.shape
+        if M != net.n_reactions or x0.shape[0] != net.n_species or \
+                (x0.ndim == 2 and x0.shape[1] != T):
+            raise ValueError("rates must be [M][T], x0 [N] or [N][T]")
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be 'fp64' or 'fp32'")
+        j = ServeJob()
+        j.net, j.n_traj = net.handle.value, T
+        j.rates, j.x0, j.x0_per_traj = rates.ctypes.data, x0.ctypes.data, int(x0.ndim == 2)
+        j.times, j.n_times = times.ctypes.data, len(times)
+        lib().rn_sweep_args_init(C.byref(j.params))
+        p = j.params
+        p.seed = int(seed) & (2**64 - 1)
+        p.eps, p.n_c, p.ssa_factor = float(eps), int(n_c), float(ssa_factor)
+        p.ssa_burst, p.max_steps, p.method = int(ssa_burst), int(max_steps), int(method)
+        p.precision, p.cle_threshold = PRECISIONS[precision], float(cle_threshold)
+        jid = C.c_int64()
+        _check(lib().rn_server_submit(self.handle, C.byref(j), C.byref(jid)), "rn_server_submit")
+        self._jobs[jid.value] = (net, len(times), net.n_species, T)
+        return jid.value
+
+    def poll(self, max_ids=1024):
+        ids = np.zeros(max_ids, dtype=np.int64)
+        n = C.c_int32()
+        _check(lib().rn_server_poll(self.handle, ids.ctypes.data, int(max_ids), C.byref(n)),
+               "rn_server_poll")
+        return [int(v) for v in ids[:n.value]]
+
+    def fetch(self, job_id):
+        net, S, N, T = self._jobs[job_id]
+        out = np.empty((S, N, T), dtype=np.int32)
+        st = np.empty((T, 4), dtype=np.uint64)
+        _check(lib().rn_server_fetch(self.handle, int(job_id), out.ctypes.data, st.ctypes.data),
+               "rn_server_fetch")
+        del self._jobs[job_id]
+        return out, st
+
+    def status(self):
+        q, r, b = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().rn_server_status(self.handle, C.byref(q), C.byref(r), C.byref(b)),
+               "rn_server_status")
+        return {"queued": q.value, "running": r.value, "bytes_in_use": b.value}
+
+    def close(self):
+        if self.handle:
+            lib().rn_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def precompile(nets, n_traj, precision="fp64", threads=8):
+    """Compile the kernels of several networks concurrently (the library lets
+    different networks compile in parallel; ctypes releases the GIL).  Returns
+    the kernel kinds, in order."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    n_traj = list(n_traj) if hasattr(n_traj, "__len__") else [n_traj] * len(nets)
+    with ThreadPoolExecutor(max_workers=max(1, int(threads))) as ex:
+        return list(ex.map(lambda a: sweep_kernel_kind(a[0], a[1], precision),
+                           zip(nets, n_traj)))
 
 
 def validate_times(times):

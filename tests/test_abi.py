@@ -141,3 +141,35 @@ def test_binding_refuses_unknown_precision():
     with pytest.raises(ValueError):
         rn.sweep(None, z, z, z, z, torch.zeros((1, 4), dtype=torch.int64), seed=1,
                  precision="fp16")
+
+
+def test_batch_handle_without_device():
+    L = rn.lib()
+    h = C.c_void_p()
+    assert L.rn_batch_create(C.byref(h)) == rn.RN_OK and h.value
+    assert L.rn_batch_size(h) == 0
+    assert L.rn_batch_launch(h, None) == rn.RN_OK  # nothing to launch
+    a = rn.SweepArgs()
+    L.rn_sweep_args_init(C.byref(a))
+    assert L.rn_batch_add(h, None, C.byref(a)) == rn.RN_E_INVALID_ARG
+    assert L.rn_batch_add(None, None, C.byref(a)) == rn.RN_E_INVALID_ARG
+    assert L.rn_batch_create(None) == rn.RN_E_INVALID_ARG
+    assert L.rn_batch_size(None) == rn.RN_E_INVALID_ARG
+    L.rn_batch_free(h)
+    L.rn_batch_free(None)
+
+
+def test_server_argument_errors_without_device():
+    L = rn.lib()
+    h = C.c_void_p()
+    assert L.rn_server_create(0, 1, C.byref(h)) == rn.RN_E_INVALID_ARG
+    assert L.rn_server_create(1 << 20, 0, C.byref(h)) == rn.RN_E_INVALID_ARG
+    assert L.rn_server_create(1 << 20, 1, None) == rn.RN_E_INVALID_ARG
+    import torch
+    if not torch.cuda.is_available():
+        assert L.rn_server_create(1 << 20, 1, C.byref(h)) == rn.RN_E_DEVICE
+    n = C.c_int32()
+    assert L.rn_server_poll(None, None, 0, C.byref(n)) == rn.RN_E_INVALID_ARG
+    assert L.rn_server_fetch(None, 1, None, None) == rn.RN_E_INVALID_ARG
+    assert L.rn_server_submit(None, None, None) == rn.RN_E_INVALID_ARG
+    L.rn_server_free(None)

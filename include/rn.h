@@ -162,6 +162,12 @@ typedef struct {
    * first PTRS block), floored at 0 -- the CLE-based approximation of the
    * paper's Methods section, in place of the Poisson draw. */
   double cle_threshold;
+  /* Optional profile (null: off): device uint64 [ceil(n_traj / 64)][4], filled
+   * per wave with the shader-clock cycles spent in SSA events, in the decide
+   * phase, in leap attempts, and in total -- only by the network-compiled
+   * kernel when the process environment sets RN_PHASE_TIMERS=1 (a separately
+   * compiled kernel; the results are unchanged).  Otherwise left untouched. */
+  uint64_t *phase_cycles;
 } rn_sweep_args;
 
 /* Defaults: eps 0.03, n_c 10, ssa_factor 10, ssa_burst 100, max_steps 1e8,
@@ -217,9 +223,10 @@ void rn_batch_free(rn_batch *b);
  * until its results are fetched.  Jobs are admitted in submission order as soon
  * as a block and one of `max_running` stream slots are free, so jobs submitted
  * while others run overlap on the device.  Work advances inside the calls
- * (there is no server thread): call rn_server_poll regularly.  A job uses its
- * network's compiled kernel when the process already has it and the generic
- * kernel otherwise (same results), starting the compilation in the background.
+ * (there is no server thread): call rn_server_poll regularly.  Submission starts
+ * compiling the job's network kernel in the background (a few worker threads);
+ * the job uses it if it is ready when the job is admitted, else the generic
+ * kernel (same results).
  * Each job's results equal those of rn_sweep with the same inputs and options.
  *
  *  rn_serve_job   host inputs, copied at submission (the caller may free them

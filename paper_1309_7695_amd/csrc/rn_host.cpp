@@ -432,6 +432,7 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   p.method = a->method;
   p.cle_threshold = a->cle_threshold;
   p.theta = sched_theta();
+  p.phase_cycles = a->phase_cycles;
   plan.wg = a->n_traj >= (int64_t)256 * n_cu ? 256 : 64;
   plan.fn = network_kernel(net, a->precision, plan.wg, wait_compile);
   if (plan.fn) {
@@ -449,6 +450,14 @@ hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
 }
 
 int device_status(hipError_t e) { return e == hipSuccess ? RN_OK : device_error(e); }
+
+void prefetch_kernel(const rn_network* net, int32_t precision, int64_t n_traj) {
+  int dev = -1, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != net->device) return;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return;
+  (void)network_kernel(net, precision, n_traj >= (int64_t)256 * n_cu ? 256 : 64, false);
+}
 
 }  // namespace rn_internal
 

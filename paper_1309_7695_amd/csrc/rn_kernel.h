@@ -72,6 +72,7 @@ struct SweepParams {
   // waits for them (or no lane is in an SSA burst).  Scheduling only: results do
   // not depend on it.
   float theta;
+  uint64_t* phase_cycles;  // optional per-wave phase profile (network-compiled kernel)
 };
 
 // Reaction-rate-equation sweep (Dormand-Prince 5(4) per lane).

@@ -227,6 +227,17 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
     if (s == S) mode = kDone;
   }
 
+#ifdef RN_NET_TIMERS
+  // shader-clock cycles per phase for this wave: SSA, decide, leap, total
+  uint64_t tph[4] = {0, 0, 0, 0}, tmark = 0;
+  const uint64_t tstart = clock64();
+#define RN_TB() (tmark = clock64())
+#define RN_TE(k) (tph[k] += clock64() - tmark)
+#else
+#define RN_TB() ((void)0)
+#define RN_TE(k) ((void)0)
+#endif
+
   for (;;) {
     const uint64_t act = __ballot(mode != kDone);
     if (act == 0) break;
@@ -237,6 +248,8 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
                                                 p.theta * (float)__popcll(act));
 
     // ---------------- one exact SSA event ----------------
+    const bool ph_ssa = in_ssa != 0;
+    if (ph_ssa) RN_TB();
     if (mode == kSsa) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
@@ -283,10 +296,13 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
         if (!ssa_only && --burst_left == 0) mode = kDecide;
       } while (false);
     }
+    if (ph_ssa) RN_TE(0);
 
     if (!leap_turn) continue;
 
     // ---------------- decide: propensities, critical set, tau' ----------------
+    const bool ph_dec = __any(mode == kDecide);
+    if (ph_dec) RN_TB();
     if (mode == kDecide) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
@@ -338,8 +354,11 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
         mode = kLeap;
       } while (false);
     }
+    if (ph_dec) RN_TE(1);
 
     // ---------------- one leap attempt ----------------
+    const bool ph_leap = __any(mode == kLeap);
+    if (ph_leap) RN_TB();
     if (mode == kLeap) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
@@ -507,7 +526,17 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
         mode = kDecide;
       } while (false);
     }
+    if (ph_leap) RN_TE(2);
   }
+#ifdef RN_NET_TIMERS
+  tph[3] = clock64() - tstart;
+  if (p.phase_cycles && (tid & 63) == 0) {
+    uint64_t* o = p.phase_cycles + (tl >> 6) * 4;
+    for (int k = 0; k < 4; ++k) o[k] = tph[k];
+  }
+#endif
+#undef RN_TB
+#undef RN_TE
 
   if (valid) {
     uint64_t* st = p.stats + tl * 4;

@@ -26,5 +26,8 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
 hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream);
 // RN_OK for hipSuccess, else RN_E_DEVICE (recording the HIP code).
 int device_status(hipError_t e);
+// Start compiling the network's kernel in the background if it is not cached
+// (the launch shape follows n_traj as in plan_sweep).
+void prefetch_kernel(const rn_network* net, int32_t precision, int64_t n_traj);
 
 }  // namespace rn_internal

@@ -9,9 +9,10 @@
 // jobs admitted while others run overlap on the device.  Progress happens
 // inside the calls (submit, poll, fetch): there is no server thread.
 //
-// A job never waits for its network's kernel to compile: it runs the compiled
-// kernel if the cache has it, else the generic kernel (identical results)
-// while the compilation proceeds in the background for later jobs.
+// A job never waits for its network's kernel to compile: the compilation
+// starts in the background when the job is submitted, and the job runs the
+// compiled kernel if it is ready by admission, else the generic kernel
+// (identical results).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -137,8 +138,8 @@ int start(rn_server* s, Job* j, int k) {
   e = rn_internal::launch_plan(plan, st);
   if (e == hipSuccess) e = hipEventRecord(j->done, st);
   if (e != hipSuccess) return rn_internal::device_status(e);
-  // the host copies are no longer needed once the copies have run; the
-  // stream orders them before the kernel, so wait only for the copies
+  // the asynchronous copies read the job's host vectors, which are kept until
+  // the job's event completes (progress releases them then)
   return RN_OK;
 }
 
@@ -241,6 +242,7 @@ int rn_server_submit(rn_server* s, const rn_serve_job* job, int64_t* job_id) {
   {
     rn_sweep_args a = j->params;
     a.n_traj = 0;
+    a.n_times = job->n_times;
     rn_internal::SweepPlan probe;
     const int rc = rn_internal::plan_sweep(job->net, &a, probe, false);
     if (rc != RN_OK) return rc;
@@ -259,6 +261,7 @@ int rn_server_submit(rn_server* s, const rn_serve_job* job, int64_t* job_id) {
   j->bytes = o;
   if (j->bytes > s->cap) return RN_E_NOMEM;
   if (hipEventCreateWithFlags(&j->done, hipEventDisableTiming) != hipSuccess) return RN_E_DEVICE;
+  rn_internal::prefetch_kernel(job->net, job->params.precision, job->n_traj);
   j->id = s->next_id++;
   *job_id = j->id;
   Job* raw = j.get();

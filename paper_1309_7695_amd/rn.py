@@ -51,7 +51,8 @@ class SweepArgs(C.Structure):
                 ("stats", C.c_void_p), ("seed", C.c_uint64),
                 ("eps", C.c_double), ("n_c", C.c_int32), ("ssa_factor", C.c_double),
                 ("ssa_burst", C.c_int32), ("max_steps", C.c_uint64),
-                ("method", C.c_int32), ("precision", C.c_int32), ("cle_threshold", C.c_double)]
+                ("method", C.c_int32), ("precision", C.c_int32), ("cle_threshold", C.c_double),
+                ("phase_cycles", C.c_void_p)]
 
 
 class ServeJob(C.Structure):
@@ -202,7 +203,7 @@ class Network:
 
 def sweep_args(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
                n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
-               cle_threshold=0.0, precision="fp64"):
+               cle_threshold=0.0, precision="fp64", phase_cycles=None):
     """Check the tensors and marshal an ``rn_sweep_args`` for them.
 
     ``rates`` float64 [M][>=T] (row stride = ld), ``x0`` int32 [N] or [N][>=T],
@@ -257,6 +258,12 @@ def sweep_args(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=
     a.ssa_burst, a.max_steps, a.method, a.precision = int(ssa_burst), int(max_steps), \
         int(method), PRECISIONS[precision]
     a.cle_threshold = float(cle_threshold)
+    if phase_cycles is not None:
+        if not phase_cycles.is_cuda or phase_cycles.dtype not in (torch.int64, torch.uint64) or \
+                phase_cycles.numel() < 4 * ((T + 63) // 64) or not phase_cycles.is_contiguous():
+            raise ValueError("phase_cycles must be a contiguous 64-bit device tensor "
+                             "of at least 4 * ceil(T / 64) entries")
+        a.phase_cycles = phase_cycles.data_ptr()
     return a
 
 

@@ -28,7 +28,7 @@ METRIC = "trajectory-steps/sec at 65,536 sims (1 GPU); p50/p99 sweep-job latency
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_kernel_synthetic_50x100_fp64_traffic.json")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "rn_net_sweep_synthetic_50x100_fp64_traffic.json")
 
 
 def measured_traffic(kind):
@@ -89,10 +89,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
-    ap.add_argument("--workload", choices=("synthetic", "batch", "serve"), default="synthetic",
+    ap.add_argument("--workload", choices=("synthetic", "batch", "serve", "phases", "copy"),
+                    default="synthetic",
                     help="synthetic: the 50x100 sweep of 65,536 trajectories (the headline); "
                          "batch: the uneven batch of 64 networks, batched vs one sweep at a "
-                         "time; serve: a Poisson stream of sweep jobs through rn_server")
+                         "time; serve: a Poisson stream of sweep jobs through rn_server; "
+                         "phases: per-phase cycle profile of the 50x100 sweep; copy: three 1 GiB "
+                         "device copies (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--batch-networks", type=int, default=64)
     ap.add_argument("--serve-jobs", type=int, default=1050)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
@@ -100,7 +103,7 @@ def parse():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="scale of trajectories and t_end per job (1 = the stated stream)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=16)
     return ap.parse_args()
 
 
@@ -164,6 +167,54 @@ def serve_main(args, torch, gen, rn):
         "overloaded": bool(achieved < 0.95 * offered),
     }
     print(json.dumps(result), flush=True)
+
+
+def copy_main(args, torch):
+    """Three device copies of 1 GiB (torch's copy kernel): the reference the
+    FETCH_SIZE and WRITE_SIZE counters are scaled by."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 3
+    print(json.dumps({"workload": "device copy", "bytes": 4 * n, "copies": 3,
+                      "ms_per_copy": dt * 1e3, "GB_per_s": 2 * 4 * n / dt / 1e9}), flush=True)
+
+
+def phases_main(args, torch, gen, rn):
+    """Per-wave shader-clock cycles of the 50x100 sweep in SSA events, the decide
+    phase and leap attempts (network-compiled kernel built with phase timers)."""
+    os.environ["RN_PHASE_TIMERS"] = "1"  # read when the kernel is compiled
+    dev = torch.device("cuda:0")
+    w = gen.synthetic_workload(n_traj=args.n_traj)
+    T = w.n_traj
+    net = rn.Network(w.net)
+    kind = rn.sweep_kernel_kind(net, T, args.precision)
+    r = torch.from_numpy(w.rates).to(dev)
+    x = torch.from_numpy(w.x0).to(dev)
+    tm = torch.from_numpy(w.times).to(dev)
+    o = torch.empty((len(w.times), w.net.n_species, T), dtype=torch.int32, device=dev)
+    st = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    ph = torch.zeros(((T + 63) // 64) * 4, dtype=torch.int64, device=dev)
+    rn.sweep(net, r, x, tm, o, st, seed=w.seed, precision=args.precision, phase_cycles=ph)
+    torch.cuda.synchronize()
+    d = ph.cpu().numpy().reshape(-1, 4).astype(float)
+    s = st.cpu().numpy()
+    tot = d[:, 3].sum()
+    waves_ssa = s[:, 1].reshape(-1, 64).max(axis=1).sum() if T % 64 == 0 else None
+    waves_leap = s[:, 0].reshape(-1, 64).max(axis=1).sum() if T % 64 == 0 else None
+    print(json.dumps({
+        "workload": f"{w.name} {args.precision.upper()}", "kernel": kind,
+        "cycles_per_wave": {"mean": d[:, 3].mean(), "max": d[:, 3].max()},
+        "share": {"ssa": d[:, 0].sum() / tot, "decide": d[:, 1].sum() / tot,
+                  "leap": d[:, 2].sum() / tot},
+        "cycles_per_ssa_pass": d[:, 0].sum() / waves_ssa if waves_ssa else None,
+        "cycles_per_decide_and_leap": (d[:, 1].sum() + d[:, 2].sum()) / waves_leap
+        if waves_leap else None}), flush=True)
 
 
 def batch_main(args, torch, gen, rn):
@@ -261,6 +312,11 @@ def main():
               "throughput by splitting the trajectory range).  Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload in ("batch", "serve"):
+        # many small kernels at once: give the process more hardware queues
+        # (HIP reads this when it initializes; the default is 4)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+        os.environ.setdefault("RN_BATCH_BRANCHES", "16")
     import torch
 
     from paper_1309_7695_amd import gen, rn
@@ -273,6 +329,12 @@ def main():
         return
     if args.workload == "serve":
         serve_main(args, torch, gen, rn)
+        return
+    if args.workload == "phases":
+        phases_main(args, torch, gen, rn)
+        return
+    if args.workload == "copy":
+        copy_main(args, torch)
         return
     dev = torch.device("cuda:0")
     w = gen.synthetic_workload(n_traj=args.n_traj)

@@ -194,8 +194,10 @@ int rn_sweep_kernel_kind(const rn_network *net, int32_t precision, int64_t n_tra
  * set of networks of uneven size and trajectory count) launched together.  The
  * jobs are independent parameter sweeps (paper, Aims and motivation section);
  * the first rn_batch_launch records all of them into one HIP graph as parallel
- * branches (largest jobs first, spread over a few internal streams), and every
- * later launch replays that graph with one hipGraphLaunch on `hip_stream`.
+ * branches (largest jobs first, spread over RN_BATCH_BRANCHES internal streams,
+ * default 8; give the process at least as many hardware queues through
+ * GPU_MAX_HW_QUEUES for them to run at once), and every later launch replays
+ * that graph with one hipGraphLaunch on `hip_stream`.
  * Each job's results are exactly those of rn_sweep with the same arguments.
  *
  *  rn_batch_add   validates `args` like rn_sweep (and compiles the network's

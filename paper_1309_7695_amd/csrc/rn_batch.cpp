@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -30,7 +31,14 @@ struct rn_batch {
 
 namespace {
 
-constexpr int kBranches = 4;  // parallel branches of the graph
+// Parallel branches of the graph: RN_BATCH_BRANCHES (1..64), default 8.  Kernels
+// on more branches than the process has hardware queues (GPU_MAX_HW_QUEUES)
+// share queues and run in turn.
+int branches() {
+  const char* e = std::getenv("RN_BATCH_BRANCHES");
+  const int v = e ? std::atoi(e) : 8;
+  return v >= 1 && v <= 64 ? v : 8;
+}
 
 void release(rn_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -45,7 +53,7 @@ void release(rn_batch* b) {
 
 // Record the fork, the job launches and the join on the origin stream.
 hipError_t capture(rn_batch* b) {
-  const int nb = (int)std::min<size_t>(kBranches, std::max<size_t>(1, b->plans.size()));
+  const int nb = (int)std::min<size_t>((size_t)branches(), std::max<size_t>(1, b->plans.size()));
   hipError_t e;
   for (int k = 0; k < nb + 1; ++k) {
     hipStream_t s = nullptr;

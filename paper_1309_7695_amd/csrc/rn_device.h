@@ -90,6 +90,22 @@ struct Vec16<float> {
   typedef float type __attribute__((ext_vector_type(16)));
 };
 
+// 1/k, correctly rounded, for the inversion walk (k = 1 .. kInvMax).  The
+// constant evaluator divides in IEEE round-to-nearest, so each entry is the
+// quotient 1.0 / k itself.
+template <typename R>
+struct RecipTable {
+  R v[kInvMax + 2];  // one spare entry: the walk reads one step ahead
+  constexpr RecipTable() : v() {
+    for (int k = 1; k <= kInvMax + 1; ++k) v[k] = R(1) / R(k);
+  }
+};
+template <typename R>
+__device__ __forceinline__ R recip(int k) {
+  static constexpr RecipTable<R> table{};
+  return table.v[k];
+}
+
 // Poisson(lam) for 0 < lam < 10: walk the CDF from k = 0 with one uniform,
 // p_k = p_{k-1} * (lam * (1/k)).  In FP32 the walk also stops once a term no
 // longer changes F (the CDF has saturated below u; the mass left is below the
@@ -99,9 +115,14 @@ __device__ __forceinline__ uint32_t poisson_inversion(R lam, R u) {
   R pk = Real<R>::exp_(-lam);
   R F = pk;
   int k = 0;
+  // Every lane still walking has the same k, so 1/k comes from a scalar load,
+  // issued one step ahead to hide its latency.
+  R rk = recip<R>(1);
   while (u > F && k < kInvMax) {
     k = k + 1;
-    pk = pk * (lam * (R(1) / (R)k));
+    const R r = rk;
+    rk = recip<R>(k + 1);
+    pk = pk * (lam * r);
     const R Fn = F + pk;
     if constexpr (!Real<R>::kF64) {
       if (Fn == F) break;

@@ -15,6 +15,7 @@
 // (identical results).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -76,8 +77,10 @@ struct Job {
   const rn_network* net = nullptr;
   int64_t T = 0;
   int32_t S = 0, N = 0, M = 0, x0_per_traj = 0;
-  std::vector<double> rates, times;  // host copies until admission
+  std::vector<double> rates, times;  // host copies until completion (when not pinned)
   std::vector<int32_t> x0;
+  bool pinned = false;               // inputs staged in the pinned arena instead
+  size_t pin_off = 0, pin_bytes = 0;
   rn_sweep_args params{};
   size_t bytes = 0, off = 0;
   size_t o_rates = 0, o_x0 = 0, o_times = 0, o_out = 0, o_stats = 0;  // within the block
@@ -95,8 +98,14 @@ struct rn_server {
   char* base = nullptr;
   size_t cap = 0;
   Arena arena;
+  // Pinned host staging for job inputs: copies from it are asynchronous, so
+  // admitting a job never blocks behind kernels already running.
+  char* pin = nullptr;
+  size_t pin_cap = 0;
+  Arena pin_arena;
   std::vector<hipStream_t> streams;
   std::vector<int> busy;  // running jobs per stream
+  hipStream_t copy = nullptr;  // results to the host (never behind a running job)
   int running = 0;
   int64_t next_id = 1;
   size_t in_use = 0;
@@ -111,14 +120,19 @@ namespace {
 int start(rn_server* s, Job* j, int k) {
   char* blk = s->base + j->off;
   hipStream_t st = s->streams[k];
-  hipError_t e = hipMemcpyAsync(blk + j->o_rates, j->rates.data(),
-                                j->rates.size() * sizeof(double), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(blk + j->o_x0, j->x0.data(), j->x0.size() * sizeof(int32_t),
+  hipError_t e;
+  if (j->pinned) {  // inputs are laid out in the pinned block as in the device block
+    e = hipMemcpyAsync(blk, s->pin + j->pin_off, j->pin_bytes, hipMemcpyHostToDevice, st);
+  } else {
+    e = hipMemcpyAsync(blk + j->o_rates, j->rates.data(), j->rates.size() * sizeof(double),
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(blk + j->o_times, j->times.data(), j->times.size() * sizeof(double),
-                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(blk + j->o_x0, j->x0.data(), j->x0.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(blk + j->o_times, j->times.data(), j->times.size() * sizeof(double),
+                         hipMemcpyHostToDevice, st);
+  }
   if (e != hipSuccess) return rn_internal::device_status(e);
   rn_sweep_args a = j->params;
   a.n_traj = j->T;
@@ -157,6 +171,10 @@ void progress(rn_server* s) {
     j->rates = {};
     j->x0 = {};
     j->times = {};
+    if (j->pinned) {
+      s->pin_arena.release(j->pin_off, j->pin_bytes);
+      j->pinned = false;
+    }
   }
   while (!s->queue.empty() && s->running < (int)s->streams.size()) {
     Job* j = s->queue.front();
@@ -199,12 +217,19 @@ int rn_server_create(int64_t hbm_budget_bytes, int32_t max_running, rn_server** 
   }
   s->cap = (size_t)hbm_budget_bytes / kAlign * kAlign;
   s->arena.init(s->cap);
+  s->pin_cap = std::min<size_t>(s->cap / 4, (size_t)4 << 30) / kAlign * kAlign;
+  if (s->pin_cap && hipHostMalloc((void**)&s->pin, s->pin_cap, hipHostMallocDefault) != hipSuccess) {
+    s->pin = nullptr;  // no pinned staging: inputs are copied from pageable memory
+    s->pin_cap = 0;
+  }
+  s->pin_arena.init(s->pin_cap);
   for (int k = 0; k < max_running; ++k) {
     hipStream_t st = nullptr;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) break;
     s->streams.push_back(st);
     s->busy.push_back(0);
   }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
   if (e != hipSuccess) {
     rn_server_free(s);
     return rn_internal::device_status(e);
@@ -260,6 +285,22 @@ int rn_server_submit(rn_server* s, const rn_serve_job* job, int64_t* job_id) {
   o += round_up((size_t)j->T * 4 * sizeof(uint64_t));
   j->bytes = o;
   if (j->bytes > s->cap) return RN_E_NOMEM;
+  // stage the inputs in pinned memory when there is room (same layout as the
+  // first three buffers of the device block)
+  const size_t in_bytes = j->o_out;
+  size_t po = 0;
+  if (s->pin && s->pin_arena.alloc(round_up(in_bytes), &po)) {
+    char* b = s->pin + po;
+    std::memcpy(b + j->o_rates, j->rates.data(), j->rates.size() * sizeof(double));
+    std::memcpy(b + j->o_x0, j->x0.data(), j->x0.size() * sizeof(int32_t));
+    std::memcpy(b + j->o_times, j->times.data(), j->times.size() * sizeof(double));
+    j->pinned = true;
+    j->pin_off = po;
+    j->pin_bytes = round_up(in_bytes);
+    j->rates = {};
+    j->x0 = {};
+    j->times = {};
+  }
   if (hipEventCreateWithFlags(&j->done, hipEventDisableTiming) != hipSuccess) return RN_E_DEVICE;
   rn_internal::prefetch_kernel(job->net, job->params.precision, job->n_traj);
   j->id = s->next_id++;
@@ -304,20 +345,22 @@ int rn_server_fetch(rn_server* s, int64_t job_id, int32_t* out, uint64_t* stats)
     if (e != hipSuccess) return rn_internal::device_status(e);
     progress(s);
   }
+  // Copy on the server's copy stream: the job's own stream may already run a
+  // later job, and a copy queued behind it would wait for that kernel.
   int rc = j->rc;
-  if (rc == RN_OK && out) {
-    const hipError_t e = hipMemcpy(out, s->base + j->off + j->o_out,
-                                   (size_t)j->S * j->N * j->T * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost);
-    if (e != hipSuccess) rc = rn_internal::device_status(e);
-  }
-  if (rc == RN_OK && stats) {
-    const hipError_t e = hipMemcpy(stats, s->base + j->off + j->o_stats,
-                                   (size_t)j->T * 4 * sizeof(uint64_t), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) rc = rn_internal::device_status(e);
-  }
+  hipStream_t st = s->copy;
+  hipError_t e = hipSuccess;
+  if (rc == RN_OK && out)
+    e = hipMemcpyAsync(out, s->base + j->off + j->o_out,
+                       (size_t)j->S * j->N * j->T * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (rc == RN_OK && stats && e == hipSuccess)
+    e = hipMemcpyAsync(stats, s->base + j->off + j->o_stats, (size_t)j->T * 4 * sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, st);
+  if (rc == RN_OK && e == hipSuccess) e = hipStreamSynchronize(st);
+  if (rc == RN_OK && e != hipSuccess) rc = rn_internal::device_status(e);
   s->arena.release(j->off, j->bytes);
   s->in_use -= j->bytes;
+  if (j->pinned) s->pin_arena.release(j->pin_off, j->pin_bytes);  // a job that failed to start
   (void)hipEventDestroy(j->done);
   s->jobs.erase(it);
   progress(s);
@@ -339,7 +382,9 @@ void rn_server_free(rn_server* s) {
   for (auto& kv : s->jobs)
     if (kv.second->done) (void)hipEventDestroy(kv.second->done);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  if (s->copy) (void)hipStreamDestroy(s->copy);
   if (s->base) (void)hipFree(s->base);
+  if (s->pin) (void)hipHostFree(s->pin);
   delete s;
 }
 

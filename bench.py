@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="scale of trajectories and t_end per job (1 = the stated stream)")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--serve-streams", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=12)
     return ap.parse_args()
 
 
@@ -122,19 +122,31 @@ def serve_main(args, torch, gen, rn):
     kw = dict(precision=args.precision)
     done_at, steps, start = {}, {}, None
     next_job, ids = 0, {}
+    host = {"build_job": 0.0, "load_network": 0.0, "submit": 0.0, "poll": 0.0, "fetch": 0.0}
     t0 = time.perf_counter()
     last_print = t0
     while len(done_at) < len(ws):
         now = time.perf_counter() - t0
         while next_job < len(ws) and arrivals[next_job] <= now:
+            ta = time.perf_counter()
             w = gen.serve_job(specs[next_job])
+            tb = time.perf_counter()
             nets[next_job] = rn.Network(w.net)
+            tc = time.perf_counter()
             ids[srv.submit(nets[next_job], w.rates, w.x0, w.times, seed=w.seed, **kw)] = next_job
+            td = time.perf_counter()
+            host["build_job"] += tb - ta
+            host["load_network"] += tc - tb
+            host["submit"] += td - tc
             next_job += 1
-        for jid in srv.poll():
+        ta = time.perf_counter()
+        finished = srv.poll()
+        host["poll"] += time.perf_counter() - ta
+        for jid in finished:
             k = ids.pop(jid)
+            ta = time.perf_counter()
             _, st = srv.fetch(jid)
-            del nets[k]
+            host["fetch"] += time.perf_counter() - ta
             done_at[k] = time.perf_counter() - t0
             steps[k] = int(st[:, 0].sum() + st[:, 1].sum())
         if time.perf_counter() - last_print > 10:
@@ -146,6 +158,8 @@ def serve_main(args, torch, gen, rn):
         else:
             time.sleep(0.0005)
     srv.close()
+    # network handles are freed only now: hipFree waits for the whole device
+    nets.clear()
     meas = range(min(args.serve_warmup, len(ws) - 1), len(ws))
     lat = np.array([done_at[k] - arrivals[k] for k in meas])
     span = max(done_at[k] for k in meas) - min(arrivals[k] for k in meas)
@@ -160,11 +174,13 @@ def serve_main(args, torch, gen, rn):
         "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": "Poisson stream of sweep jobs", "jobs": len(ws),
                    "rate_per_s": offered, "scale": args.serve_scale,
-                   "budget_gib": args.serve_budget_gib, "streams": args.serve_streams},
+                   "budget_gib": args.serve_budget_gib, "streams": args.serve_streams,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3,
                        "p99": float(np.percentile(lat, 99)) * 1e3},
         "jobs_per_s": {"offered": offered, "completed": achieved},
         "overloaded": bool(achieved < 0.95 * offered),
+        "host_s": host,
     }
     print(json.dumps(result), flush=True)
 
@@ -314,9 +330,11 @@ def main():
         sys.exit(2)
     if args.workload in ("batch", "serve"):
         # many small kernels at once: give the process more hardware queues
-        # (HIP reads this when it initializes; the default is 4)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
-        os.environ.setdefault("RN_BATCH_BRANCHES", "16")
+        # than it has streams (HIP reads this when it initializes; its default
+        # is 4, and streams beyond the queues share them and wait for each
+        # other's kernels)
+        os.environ["GPU_MAX_HW_QUEUES"] = "16"
+        os.environ.setdefault("RN_BATCH_BRANCHES", "12")
     import torch
 
     from paper_1309_7695_amd import gen, rn

@@ -74,7 +74,9 @@ typedef struct rn_network rn_network; /* opaque; immutable after load */
 int rn_load_network(const rn_network_desc *desc, rn_network **out);
 
 /* Release a handle and its device tables (null is ignored).  The caller must
- * make sure no sweep using it is still running. */
+ * make sure no sweep using it is still running.  Freeing device memory waits
+ * for all work on the device (hipFree), so a serving loop frees handles when
+ * the device is idle rather than after each job. */
 void rn_free_network(rn_network *net);
 
 /* Number of species / reactions of a loaded network (-1 for a null handle). */
@@ -190,6 +192,16 @@ int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream)
 int rn_sweep_kernel_kind(const rn_network *net, int32_t precision, int64_t n_traj);
 
 /*
+ * Drop the network-kernel compilations queued in the background (by
+ * rn_server_submit) that have not started, and wait for those running.  The
+ * dropped networks keep the generic kernel for the rest of the process.  Call
+ * it before the process exits if a server was used: a compilation still
+ * running while the process tears down its libraries can crash the exit.  The
+ * Python binding registers it to run at interpreter exit.
+ */
+void rn_compile_drain(void);
+
+/*
  * Batched sweeps: many jobs (each a network handle and an rn_sweep_args, e.g. a
  * set of networks of uneven size and trajectory count) launched together.  The
  * jobs are independent parameter sweeps (paper, Aims and motivation section);
@@ -221,10 +233,16 @@ void rn_batch_free(rn_batch *b);
  * Sweep-job server: jobs of different networks and sizes admitted continuously
  * into a fixed HBM budget (many parameter sweeps in flight at once: paper, Aims
  * and motivation section).  rn_server_create allocates the budget once as an
- * arena; each job holds one block of it (inputs, samples, stats) from admission
- * until its results are fetched.  Jobs are admitted in submission order as soon
- * as a block and one of `max_running` stream slots are free, so jobs submitted
- * while others run overlap on the device.  Work advances inside the calls
+ * arena, and a pinned host staging area of min(budget / 4, 4 GiB); each job
+ * holds one block of the arena (inputs, samples, stats) from admission until
+ * it completes when the staging area had room for the whole job (its results
+ * are then copied there on the job's stream), else until its results are
+ * fetched.  Jobs are admitted in submission order as soon as a block and one of
+ * `max_running` stream slots are free, so jobs submitted while others run
+ * overlap on the device.  Streams beyond the process's hardware queues
+ * (GPU_MAX_HW_QUEUES) share queues and wait for each other's work: keep
+ * max_running a few below it (the null stream, the library's upload stream and
+ * the server's copy stream take one each).  Work advances inside the calls
  * (there is no server thread): call rn_server_poll regularly.  Submission starts
  * compiling the job's network kernel in the background (a few worker threads);
  * the job uses it if it is ready when the job is admitted, else the generic

@@ -122,6 +122,9 @@ int rn_batch_add(rn_batch* b, const rn_network* net, const rn_sweep_args* args) 
   if (b->device >= 0 && dev != b->device) return RN_E_INVALID_ARG;
   b->device = dev;
   if (plan.empty) return RN_OK;
+  // the graph's kernels then read tables that are already in place
+  const hipError_t se = rn_internal::stage_network_now(net);
+  if (se != hipSuccess) return rn_internal::device_status(se);
   try {
     b->plans.push_back(plan);
     b->work.push_back((double)args->n_traj);

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -28,6 +29,13 @@ struct rn_network {
   size_t bytes = 0;
   rn::DevNet dev{};
   std::string jit_consts;  // compile-time prelude of the network-compiled kernel, or empty
+  // The device tables are filled by the first launch that uses them, on that
+  // launch's stream, from a pinned copy of the table image (see stage_network).
+  void* himg = nullptr;
+  hipEvent_t staged = nullptr;  // recorded after the copy
+  mutable std::mutex mu;
+  mutable int stage = 0;        // 0 not copied, 1 copy enqueued, 2 copy complete
+  mutable hipStream_t stage_stream = nullptr;
 };
 
 namespace {
@@ -40,6 +48,25 @@ int device_error(hipError_t e) {
 }
 
 constexpr int32_t kMaxCoeff = 1 << 20;
+
+// A library stream of the current device (one per device, created on first
+// use and kept for the process).
+hipError_t library_stream(int dev, hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipStream_t st = nullptr;
+  const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  streams.emplace(dev, st);
+  *out = st;
+  return hipSuccess;
+}
 
 // Wave scheduling knob (fraction of lanes that must wait before the leap-side
 // phases run).  RN_SCHED_THETA overrides it for tuning; results never depend on it.
@@ -307,10 +334,17 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
   net->M = desc->n_reactions;
   hipError_t e = hipGetDevice(&net->device);
   if (e != hipSuccess) { delete net; return device_error(e); }
+  // No copy here: a copy on any stream of its own can wait behind sweeps
+  // already running on the device; the first launch that uses the network
+  // copies the tables on its own stream instead.
   e = hipMalloc(&net->dbuf, img.size());
-  if (e != hipSuccess) { delete net; return e == hipErrorOutOfMemory ? RN_E_NOMEM : device_error(e); }
-  e = hipMemcpy(net->dbuf, img.data(), img.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { (void)hipFree(net->dbuf); delete net; return device_error(e); }
+  if (e == hipSuccess) e = hipHostMalloc(&net->himg, img.size(), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&net->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    rn_free_network(net);
+    return e == hipErrorOutOfMemory ? RN_E_NOMEM : device_error(e);
+  }
+  std::memcpy(net->himg, img.data(), img.size());
   net->bytes = img.size();
   unsigned char* b = (unsigned char*)net->dbuf;
   rn::DevNet& D = net->dev;
@@ -345,6 +379,8 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
 void rn_free_network(rn_network* net) {
   if (!net) return;
   if (net->dbuf) (void)hipFree(net->dbuf);
+  if (net->himg) (void)hipHostFree(net->himg);
+  if (net->staged) (void)hipEventDestroy(net->staged);
   delete net;
 }
 
@@ -363,6 +399,57 @@ static hipFunction_t network_kernel(const rn_network* net, int32_t precision, in
 }
 
 namespace rn_internal {
+
+// Make the network's device tables valid for work enqueued next on `stream`.
+// The first launch copies them on its own stream (ordered before its kernel)
+// and records an event; a launch on another stream while that copy may still
+// run waits for the event; once it has completed, nothing is enqueued.  Under
+// stream capture the copy becomes part of the graph (replays rewrite the same
+// bytes) and the handle stays unstaged for launches outside the graph.
+hipError_t stage_network(const rn_network* net, hipStream_t stream) {
+  std::lock_guard<std::mutex> lock(net->mu);
+  if (net->stage == 2) return hipSuccess;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(stream, &cs);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusNone) {
+    if (net->stage == 1) {
+      // the copy was enqueued outside the graph: wait for it before capturing
+      e = hipEventSynchronize(net->staged);
+      if (e == hipSuccess) net->stage = 2;
+      return e;
+    }
+    return hipMemcpyAsync(net->dbuf, net->himg, net->bytes, hipMemcpyHostToDevice, stream);
+  }
+  if (net->stage == 0) {
+    e = hipMemcpyAsync(net->dbuf, net->himg, net->bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(net->staged, stream);
+    if (e != hipSuccess) return e;
+    net->stage = 1;
+    net->stage_stream = stream;
+    return hipSuccess;
+  }
+  e = hipEventQuery(net->staged);
+  if (e == hipSuccess) {
+    net->stage = 2;
+    return hipSuccess;
+  }
+  if (e != hipErrorNotReady) return e;
+  return stream == net->stage_stream ? hipSuccess : hipStreamWaitEvent(stream, net->staged, 0);
+}
+
+// Stage the network now on the library stream and wait for the copy.
+hipError_t stage_network_now(const rn_network* net) {
+  hipStream_t st = nullptr;
+  hipError_t e = library_stream(net->device, &st);
+  if (e == hipSuccess) e = stage_network(net, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lock(net->mu);
+    if (net->stage == 1 && hipEventQuery(net->staged) == hipSuccess) net->stage = 2;
+  }
+  return e;
+}
 
 int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
                bool wait_compile) {
@@ -409,6 +496,7 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   cfg.lds_bytes = per_lane * cfg.wg;
   if (cfg.lds_bytes > (size_t)max_lds) return RN_E_UNSUPPORTED;
 
+  plan.net = net;
   rn::SweepParams& p = plan.p;
   p.net = net->dev;
   p.rates = a->rates;
@@ -444,6 +532,8 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
 
 hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
   if (plan.empty) return hipSuccess;
+  const hipError_t e = stage_network(plan.net, stream);
+  if (e != hipSuccess) return e;
   if (plan.fn) return rn::jit_launch(plan.fn, plan.p, plan.wg, plan.lds, stream);
   return plan.precision == RN_FP32 ? rn::launch_sweep_f32(plan.p, plan.cfg, stream)
                                    : rn::launch_sweep_f64(plan.p, plan.cfg, stream);
@@ -482,6 +572,8 @@ int rn_sweep_kernel_kind(const rn_network* net, int32_t precision, int64_t n_tra
   const int jwg = n_traj >= (int64_t)256 * n_cu ? 256 : 64;
   return network_kernel(net, precision, jwg) ? 1 : 0;
 }
+
+void rn_compile_drain(void) { rn::jit_drain(); }
 
 void rn_ode_args_init(rn_ode_args* a) {
   if (!a) return;
@@ -528,7 +620,8 @@ int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) 
   p.rtol = a->rtol;
   p.atol = a->atol;
   p.max_steps = a->max_steps;
-  e = rn::launch_ode(p, (hipStream_t)hip_stream);
+  e = rn_internal::stage_network(net, (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = rn::launch_ode(p, (hipStream_t)hip_stream);
   if (e != hipSuccess) return device_error(e);
   return RN_OK;
 }

@@ -30,6 +30,9 @@ hipFunction_t jit_kernel(const std::string& consts, int precision, int wg);
 // The compiled kernel if it is ready now; otherwise null, after starting its
 // compilation on a background thread (so a later call finds it).
 hipFunction_t jit_kernel_nowait(const std::string& consts, int precision, int wg);
+// Drop background compilations not yet started (their networks keep the
+// generic kernels) and wait for the running ones.
+void jit_drain();
 hipError_t jit_launch(hipFunction_t fn, const SweepParams& p, int wg, size_t lds,
                       hipStream_t stream);
 

@@ -9,6 +9,7 @@
 namespace rn_internal {
 
 struct SweepPlan {
+  const rn_network* net = nullptr;
   bool empty = false;          // n_traj == 0: nothing to launch
   int32_t precision = RN_FP64;
   hipFunction_t fn = nullptr;  // network-compiled kernel, or null for the generic one
@@ -23,7 +24,12 @@ struct SweepPlan {
 // (starting its compilation in the background).  Returns RN_OK or RN_E_*.
 int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
                bool wait_compile = true);
+// Enqueue the sweep on `stream` (with the network's table copy if this is its
+// first use).
 hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream);
+// Copy the network's tables on the library stream now and wait for the copy
+// (for launches recorded into a graph).
+hipError_t stage_network_now(const rn_network* net);
 // RN_OK for hipSuccess, else RN_E_DEVICE (recording the HIP code).
 int device_status(hipError_t e);
 // Start compiling the network's kernel in the background if it is not cached

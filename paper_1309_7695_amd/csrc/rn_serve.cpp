@@ -3,11 +3,18 @@
 //
 // The device memory is one arena allocated at creation (the budget); every job
 // takes one block of it (first fit, 256-byte aligned) for its inputs, samples
-// and stats, from admission until the caller fetches the results, so serving
-// never calls hipMalloc.  Jobs are admitted strictly in arrival order whenever
-// a block and a stream slot are free; each runs on one of a few streams, so
-// jobs admitted while others run overlap on the device.  Progress happens
-// inside the calls (submit, poll, fetch): there is no server thread.
+// and stats from admission on, so serving never calls hipMalloc.  Jobs are
+// admitted strictly in arrival order whenever a block and a stream slot are
+// free; each runs on one of a few streams, so jobs admitted while others run
+// overlap on the device.  Progress happens inside the calls (submit, poll,
+// fetch): there is no server thread.
+//
+// Host traffic stays on the job's own stream: when the pinned staging arena
+// has room for the whole job, its inputs are copied from there before the
+// kernel and its results back into it right after, so the device block is
+// free again as soon as the job completes and fetching is a host memcpy.  A
+// stream serves one job after another, and a copy queued on a stream that is
+// already running a later job would wait for that kernel.
 //
 // A job never waits for its network's kernel to compile: the compilation
 // starts in the background when the job is submitted, and the job runs the
@@ -80,7 +87,9 @@ struct Job {
   std::vector<double> rates, times;  // host copies until completion (when not pinned)
   std::vector<int32_t> x0;
   bool pinned = false;               // inputs staged in the pinned arena instead
+  bool pin_out = false;              // ... and results too (the block has the device layout)
   size_t pin_off = 0, pin_bytes = 0;
+  bool dev_held = false;             // holds its device block
   rn_sweep_args params{};
   size_t bytes = 0, off = 0;
   size_t o_rates = 0, o_x0 = 0, o_times = 0, o_out = 0, o_stats = 0;  // within the block
@@ -105,7 +114,7 @@ struct rn_server {
   Arena pin_arena;
   std::vector<hipStream_t> streams;
   std::vector<int> busy;  // running jobs per stream
-  hipStream_t copy = nullptr;  // results to the host (never behind a running job)
+  hipStream_t copy = nullptr;  // results of jobs without pinned results (never behind a job)
   int running = 0;
   int64_t next_id = 1;
   size_t in_use = 0;
@@ -150,11 +159,31 @@ int start(rn_server* s, Job* j, int k) {
   int rc = rn_internal::plan_sweep(j->net, &a, plan, /*wait_compile=*/false);
   if (rc != RN_OK) return rc;
   e = rn_internal::launch_plan(plan, st);
+  if (e == hipSuccess && j->pin_out)
+    e = hipMemcpyAsync(s->pin + j->pin_off + j->o_out, blk + j->o_out,
+                       (size_t)j->S * j->N * j->T * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && j->pin_out)
+    e = hipMemcpyAsync(s->pin + j->pin_off + j->o_stats, blk + j->o_stats,
+                       (size_t)j->T * 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipEventRecord(j->done, st);
   if (e != hipSuccess) return rn_internal::device_status(e);
   // the asynchronous copies read the job's host vectors, which are kept until
   // the job's event completes (progress releases them then)
   return RN_OK;
+}
+
+void release_device(rn_server* s, Job* j) {
+  if (!j->dev_held) return;
+  s->arena.release(j->off, j->bytes);
+  s->in_use -= j->bytes;
+  j->dev_held = false;
+}
+
+void release_pinned(rn_server* s, Job* j) {
+  if (!j->pinned) return;
+  s->pin_arena.release(j->pin_off, j->pin_bytes);
+  j->pinned = false;
+  j->pin_out = false;
 }
 
 // Retire finished jobs and admit queued ones in arrival order.
@@ -171,10 +200,10 @@ void progress(rn_server* s) {
     j->rates = {};
     j->x0 = {};
     j->times = {};
-    if (j->pinned) {
-      s->pin_arena.release(j->pin_off, j->pin_bytes);
-      j->pinned = false;
-    }
+    if (j->pin_out && j->rc == RN_OK)
+      release_device(s, j);  // the results are in the pinned block
+    else
+      release_pinned(s, j);  // inputs only (or nothing to keep)
   }
   while (!s->queue.empty() && s->running < (int)s->streams.size()) {
     Job* j = s->queue.front();
@@ -182,6 +211,7 @@ void progress(rn_server* s) {
     if (!s->arena.alloc(j->bytes, &off)) break;  // wait for memory, in order
     s->queue.pop_front();
     j->off = off;
+    j->dev_held = true;
     s->in_use += j->bytes;
     int k = 0;
     for (int q = 1; q < (int)s->busy.size(); ++q)
@@ -285,23 +315,31 @@ int rn_server_submit(rn_server* s, const rn_serve_job* job, int64_t* job_id) {
   o += round_up((size_t)j->T * 4 * sizeof(uint64_t));
   j->bytes = o;
   if (j->bytes > s->cap) return RN_E_NOMEM;
-  // stage the inputs in pinned memory when there is room (same layout as the
-  // first three buffers of the device block)
+  // Stage the job in pinned memory when there is room, with the layout of the
+  // device block: the whole job (inputs and results), else the inputs only.
   const size_t in_bytes = j->o_out;
   size_t po = 0;
-  if (s->pin && s->pin_arena.alloc(round_up(in_bytes), &po)) {
+  if (s->pin && s->pin_arena.alloc(j->bytes, &po)) {
+    j->pin_out = true;
+    j->pin_bytes = j->bytes;
+  } else if (s->pin && s->pin_arena.alloc(in_bytes, &po)) {
+    j->pin_bytes = in_bytes;
+  }
+  if (j->pin_bytes) {
     char* b = s->pin + po;
     std::memcpy(b + j->o_rates, j->rates.data(), j->rates.size() * sizeof(double));
     std::memcpy(b + j->o_x0, j->x0.data(), j->x0.size() * sizeof(int32_t));
     std::memcpy(b + j->o_times, j->times.data(), j->times.size() * sizeof(double));
     j->pinned = true;
     j->pin_off = po;
-    j->pin_bytes = round_up(in_bytes);
     j->rates = {};
     j->x0 = {};
     j->times = {};
   }
-  if (hipEventCreateWithFlags(&j->done, hipEventDisableTiming) != hipSuccess) return RN_E_DEVICE;
+  if (hipEventCreateWithFlags(&j->done, hipEventDisableTiming) != hipSuccess) {
+    release_pinned(s, j.get());
+    return RN_E_DEVICE;
+  }
   rn_internal::prefetch_kernel(job->net, job->params.precision, job->n_traj);
   j->id = s->next_id++;
   *job_id = j->id;
@@ -345,22 +383,28 @@ int rn_server_fetch(rn_server* s, int64_t job_id, int32_t* out, uint64_t* stats)
     if (e != hipSuccess) return rn_internal::device_status(e);
     progress(s);
   }
-  // Copy on the server's copy stream: the job's own stream may already run a
-  // later job, and a copy queued behind it would wait for that kernel.
   int rc = j->rc;
-  hipStream_t st = s->copy;
-  hipError_t e = hipSuccess;
-  if (rc == RN_OK && out)
-    e = hipMemcpyAsync(out, s->base + j->off + j->o_out,
-                       (size_t)j->S * j->N * j->T * sizeof(int32_t), hipMemcpyDeviceToHost, st);
-  if (rc == RN_OK && stats && e == hipSuccess)
-    e = hipMemcpyAsync(stats, s->base + j->off + j->o_stats, (size_t)j->T * 4 * sizeof(uint64_t),
-                       hipMemcpyDeviceToHost, st);
-  if (rc == RN_OK && e == hipSuccess) e = hipStreamSynchronize(st);
-  if (rc == RN_OK && e != hipSuccess) rc = rn_internal::device_status(e);
-  s->arena.release(j->off, j->bytes);
-  s->in_use -= j->bytes;
-  if (j->pinned) s->pin_arena.release(j->pin_off, j->pin_bytes);  // a job that failed to start
+  const size_t out_bytes = (size_t)j->S * j->N * j->T * sizeof(int32_t);
+  const size_t stats_bytes = (size_t)j->T * 4 * sizeof(uint64_t);
+  if (rc == RN_OK && j->pin_out) {  // the results are already in host memory
+    const char* b = s->pin + j->pin_off;
+    if (out) std::memcpy(out, b + j->o_out, out_bytes);
+    if (stats) std::memcpy(stats, b + j->o_stats, stats_bytes);
+  } else if (rc == RN_OK) {
+    // Copy on the server's copy stream: the job's own stream may already run a
+    // later job, and a copy queued behind it would wait for that kernel.
+    hipStream_t st = s->copy;
+    hipError_t e = hipSuccess;
+    if (out)
+      e = hipMemcpyAsync(out, s->base + j->off + j->o_out, out_bytes, hipMemcpyDeviceToHost, st);
+    if (stats && e == hipSuccess)
+      e = hipMemcpyAsync(stats, s->base + j->off + j->o_stats, stats_bytes,
+                         hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = rn_internal::device_status(e);
+  }
+  release_device(s, j);
+  release_pinned(s, j);
   (void)hipEventDestroy(j->done);
   s->jobs.erase(it);
   progress(s);

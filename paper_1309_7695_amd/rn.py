@@ -7,6 +7,7 @@ anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -27,7 +28,7 @@ FP64, FP32 = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
-           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_sweep_kernel_kind",
+           "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_sweep_kernel_kind", "rn_compile_drain",
            "rn_batch_create", "rn_batch_add", "rn_batch_size", "rn_batch_launch", "rn_batch_free",
            "rn_server_create", "rn_server_submit", "rn_server_poll", "rn_server_fetch",
            "rn_server_status", "rn_server_free",
@@ -105,6 +106,8 @@ def lib():
         L.rn_sweep.restype = C.c_int
         L.rn_sweep_kernel_kind.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
         L.rn_sweep_kernel_kind.restype = C.c_int
+        L.rn_compile_drain.argtypes = []
+        L.rn_compile_drain.restype = None
         L.rn_batch_create.argtypes = [C.POINTER(C.c_void_p)]
         L.rn_batch_create.restype = C.c_int
         L.rn_batch_add.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SweepArgs)]
@@ -142,6 +145,8 @@ def lib():
         L.rn_last_device_error.argtypes = []
         L.rn_last_device_error.restype = C.c_int
         _lib = L
+        # background compilations end before the interpreter tears down
+        atexit.register(L.rn_compile_drain)
     return _lib
 
 

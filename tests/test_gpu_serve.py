@@ -71,3 +71,30 @@ def test_server_rejects_job_over_budget():
         srv.submit(rn.Network(w.net), w.rates, w.x0, w.times, seed=1)
     assert e.value.code == rn.RN_E_NOMEM
     srv.close()
+
+
+def test_server_pinned_results_free_the_device_block():
+    """With staging room for every whole job, each job's results go to pinned
+    host memory on its own stream: the device budget is free again as soon as
+    the jobs complete (before any fetch), and the fetched results equal the
+    same jobs run alone."""
+    arrivals, ws = gen.serve_jobs(n_jobs=6, seed=5200, t_scale=0.02, t_end_scale=0.02,
+                                  n_samples=11)
+    budget = 8 * sum(_job_bytes(w) for w in ws)  # staging area: 2x all jobs
+    nets = [rn.Network(w.net) for w in ws]
+    srv = rn.Server(budget, max_running=4)
+    ids = [srv.submit(nets[k], w.rates, w.x0, w.times, seed=60 + k) for k, w in enumerate(ws)]
+    done = set()
+    t0 = time.time()
+    while len(done) < len(ids):
+        done.update(srv.poll())
+        assert time.time() - t0 < 240, "server made no progress"
+        time.sleep(0.001)
+    assert srv.status() == {"queued": 0, "running": 0, "bytes_in_use": 0}
+    got = {jid: srv.fetch(jid) for jid in ids}
+    srv.close()
+    for k, w in enumerate(ws):
+        out, st = rn.run(nets[k], w.rates, w.x0, w.times, seed=60 + k)
+        assert np.array_equal(got[ids[k]][0], out), k
+        assert np.array_equal(got[ids[k]][1], st), k
+    _say(f"  {len(ws)} jobs with pinned results identical to alone")

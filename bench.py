@@ -328,13 +328,16 @@ def main():
               "throughput by splitting the trajectory range).  Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
-    if args.workload in ("batch", "serve"):
-        # many small kernels at once: give the process more hardware queues
-        # than it has streams (HIP reads this when it initializes; its default
-        # is 4, and streams beyond the queues share them and wait for each
-        # other's kernels)
-        os.environ["GPU_MAX_HW_QUEUES"] = "16"
-        os.environ.setdefault("RN_BATCH_BRANCHES", "12")
+    if args.workload == "serve":
+        # one hardware queue per server stream, plus the null, copy and table
+        # streams (HIP reads this when it initializes; its default is 4, and
+        # streams beyond the queues share them and wait for each other's work)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, args.serve_streams + 4))
+    if args.workload == "batch":
+        # graph branches (the graph's launch spreads them over the process's
+        # hardware queues; 16 branches on HIP's default 4 queues ran the batch
+        # in 84 s, 12 branches on 16 queues in 105 s)
+        os.environ.setdefault("RN_BATCH_BRANCHES", "16")
     import torch
 
     from paper_1309_7695_amd import gen, rn

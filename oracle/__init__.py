@@ -40,6 +40,11 @@ class _OdeParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
 
 
+class _HybridParams(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("rtol", C.c_double), ("atol", C.c_double),
+                ("max_steps", C.c_uint64)]
+
+
 OPS_FIELDS = ["leaps", "ssa_events", "rejections", "prop_evals", "crit_tests", "tau_terms",
               "tau_species", "philox_blocks", "inv_draws", "inv_iters", "ptrs_draws",
               "ptrs_iters", "ptrs_log_tests", "exp_draws", "select_terms", "update_terms"]
@@ -77,6 +82,10 @@ def lib():
                                   C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
                                   C.c_void_p, C.c_void_p]
         L.orc_ode_run.restype = C.c_int
+        L.orc_hybrid_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
+                                     C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_hybrid_run.restype = C.c_int
         _lib = L
     return _lib
 
@@ -211,6 +220,57 @@ def ode_run(net, rates, x0, times, *, rtol=1e-6, atol=1e-6, max_steps=10**7, tra
             xp, xld = x0.ctypes.data, 0
         return L.orc_ode_run(C.byref(desc), rp, T, xp, xld, times.ctypes.data, S, hi - lo,
                              out.ctypes.data + 8 * lo, n, stats.ctypes.data + 32 * lo, C.byref(par))
+
+    if nth == 1:
+        rcs = [work(0)]
+    else:
+        with ThreadPoolExecutor(nth) as ex:
+            rcs = list(ex.map(work, range(nth)))
+    for rc in rcs:
+        if rc != 0:
+            raise RuntimeError(f"oracle error {rc}")
+    del keep
+    return out, stats
+
+
+def hybrid_run(net, continuous, rates, x0, times, *, seed, rtol=1e-6, atol=1e-6,
+               max_steps=10**7, traj_range=None, threads=1):
+    """Hybrid stochastic/deterministic sweep (piecewise-deterministic Markov
+    process) for trajectories ``traj_range``: reactions with ``continuous[j]``
+    true form the flow, the others fire as jumps.
+
+    Returns ``(out [S][N][T] float64, stats [T][4] uint64)`` with stats =
+    (accepted steps, rejected steps and jump-location trials, jumps, status)."""
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    M, T = rates.shape
+    cont = np.ascontiguousarray(np.asarray(continuous, dtype=bool).astype(np.int32))
+    if cont.shape != (M,):
+        raise ValueError("continuous must have one entry per reaction")
+    a, b = traj_range if traj_range is not None else (0, T)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    S, N = len(times), net.n_species
+    n = b - a
+    out = np.zeros((S, N, n), dtype=np.float64)
+    stats = np.zeros((n, 4), dtype=np.uint64)
+    desc, keep = _desc(net)
+    par = _HybridParams(int(seed), float(rtol), float(atol), int(max_steps))
+    L = lib()
+    nth = max(1, min(int(threads), n)) if n > 0 else 1
+    bounds = np.linspace(0, n, nth + 1).astype(np.int64)
+
+    def work(ci):
+        lo, hi = int(bounds[ci]), int(bounds[ci + 1])
+        if hi <= lo:
+            return 0
+        rp = rates.ctypes.data + 8 * (a + lo)
+        if x0.ndim == 2:
+            xp, xld = x0.ctypes.data + 4 * (a + lo), T
+        else:
+            xp, xld = x0.ctypes.data, 0
+        return L.orc_hybrid_run(C.byref(desc), cont.ctypes.data, rp, T, xp, xld,
+                                times.ctypes.data, S, a + lo, hi - lo, out.ctypes.data + 8 * lo,
+                                n, stats.ctypes.data + 32 * lo, C.byref(par))
 
     if nth == 1:
         rcs = [work(0)]

@@ -16,6 +16,27 @@
  * a rejection the growth factor is capped at 1).  The first step is
  * 0.01 * rms(y/sc) / rms(f/sc) (1e-6 when either norm is below 1e-5).  A step
  * that reaches the next sample time ends exactly on it.
+ *
+ * Hybrid stochastic/deterministic sweep (paper, Methods section: abundant
+ * species follow the mean-field equations while low-amount species keep their
+ * random fluctuations; the process is a piecewise-deterministic Markov process,
+ * M. H. A. Davis, J. R. Stat. Soc. B 46 (1984) 353).  The caller partitions the
+ * reactions: continuous ones drive the flow dy/dt = sum_{j in C} nu_j a_j(y)
+ * (the rates above), discrete ones fire as jumps y += nu_j with intensities
+ * a_j = max(0, c_j * h_j(y)), h_j = 1, y_a, y_a*y_b or y_a*(y_a-1)/2 (the
+ * stochastic mass-action forms).  Jump times follow the integrated-intensity
+ * construction of hybrid methods such as Salis and Kaznessis (J. Chem. Phys.
+ * 122, 054103 (2005)): with xi ~ Exp(1), the next jump comes when
+ * L(t) = integral of a0_D(y) since the last jump reaches xi.  L is integrated
+ * with y by the same Dormand-Prince step (its own error term enters the norm as
+ * max(rms over species, |e_L| / sc_L)); when an accepted step carries L past
+ * xi, its length is searched from the same start by the Illinois variant of
+ * regula falsi (M. Dowell, P. Jarratt, BIT 11 (1971) 168) on g = L - xi until
+ * |g| <= 1e-12 (1 + xi) or 30 trials, and the jump fires at the end of the last
+ * trial.  The jumping reaction is the first discrete j
+ * with u * a0_D < a_1 + ... + a_j at that state.  Jump k of trajectory tr draws
+ * (xi, u) from Philox4x32-10 block (tr, k, 0, 0x80000000): xi = -log(1 - u53(w0,
+ * w1)), u = u53(w2, w3).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -202,6 +223,254 @@ int orc_ode_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
     stats[t * 4 + 0] = acc;
     stats[t * 4 + 1] = rej;
     stats[t * 4 + 2] = 0;
+    stats[t * 4 + 3] = status;
+  }
+  free(w);
+  dnet_free(&g);
+  return ORC_OK;
+}
+
+/* a_j of discrete reaction j at y (stochastic mass-action form, floored at 0). */
+static double hybrid_intensity(const dnet *g, int j, const double *c, int64_t cld,
+                               const double *y) {
+  double h;
+  switch (g->kind[j]) {
+    case 0: h = 1.0; break;
+    case 1: h = y[g->ra[j]]; break;
+    case 2: h = y[g->ra[j]] * y[g->rb[j]]; break;
+    default: h = 0.5 * (y[g->ra[j]] * (y[g->ra[j]] - 1.0)); break;
+  }
+  double a = c[(int64_t)j * cld] * h;
+  return a > 0.0 ? a : 0.0;
+}
+
+/* Flow f_y (continuous reactions, species-major in increasing j) and the
+ * discrete intensity a0_D (increasing j) at y. */
+static double hybrid_rhs(const dnet *g, const int32_t *cont, const double *c, int64_t cld,
+                         const double *y, double *f) {
+  for (int i = 0; i < g->N; ++i) f[i] = 0.0;
+  double a0 = 0.0;
+  for (int j = 0; j < g->M; ++j) {
+    double h;
+    if (cont[j]) {
+      switch (g->kind[j]) {
+        case 0: h = 1.0; break;
+        case 1: h = y[g->ra[j]]; break;
+        case 2: h = y[g->ra[j]] * y[g->rb[j]]; break;
+        default: h = 0.5 * (y[g->ra[j]] * y[g->ra[j]]); break;
+      }
+      double a = c[(int64_t)j * cld] * h;
+      for (int i = 0; i < g->N; ++i) {
+        int v = g->nu[(size_t)j * g->N + i];
+        if (v) f[i] = f[i] + (double)v * a;
+      }
+    } else {
+      a0 = a0 + hybrid_intensity(g, j, c, cld, y);
+    }
+  }
+  return a0;
+}
+
+#define HYB_STREAM 0x80000000u
+#define HYB_LOCATE_MAX 30
+#define HYB_LOCATE_TOL 1e-12
+
+/* One Dormand-Prince step of length hu from (y, L) with k1 = f(y), kl1 = a0_D(y):
+ * yn, Ln, the stage derivatives k2..k7 (k7 = f(yn), kl[6] = a0_D(yn)) and the
+ * error norm. */
+static double hybrid_step(const dnet *g, const int32_t *cont, const double *c, int64_t cld,
+                          const orc_hybrid_params *par, double hu, const double *y, double L,
+                          const double *k1, double *k2, double *k3, double *k4, double *k5,
+                          double *k6, double *k7, double *ys, double *yn, double *kl,
+                          double *Ln) {
+  const int N = g->N;
+  for (int i = 0; i < N; ++i) ys[i] = y[i] + hu * (A21 * k1[i]);
+  kl[1] = hybrid_rhs(g, cont, c, cld, ys, k2);
+  for (int i = 0; i < N; ++i) ys[i] = y[i] + hu * (A31 * k1[i] + A32 * k2[i]);
+  kl[2] = hybrid_rhs(g, cont, c, cld, ys, k3);
+  for (int i = 0; i < N; ++i) ys[i] = y[i] + hu * (A41 * k1[i] + A42 * k2[i] + A43 * k3[i]);
+  kl[3] = hybrid_rhs(g, cont, c, cld, ys, k4);
+  for (int i = 0; i < N; ++i)
+    ys[i] = y[i] + hu * (A51 * k1[i] + A52 * k2[i] + A53 * k3[i] + A54 * k4[i]);
+  kl[4] = hybrid_rhs(g, cont, c, cld, ys, k5);
+  for (int i = 0; i < N; ++i)
+    ys[i] = y[i] + hu * (A61 * k1[i] + A62 * k2[i] + A63 * k3[i] + A64 * k4[i] + A65 * k5[i]);
+  kl[5] = hybrid_rhs(g, cont, c, cld, ys, k6);
+  for (int i = 0; i < N; ++i)
+    yn[i] = y[i] + hu * (B1 * k1[i] + B3 * k3[i] + B4 * k4[i] + B5 * k5[i] + B6 * k6[i]);
+  kl[6] = hybrid_rhs(g, cont, c, cld, yn, k7);
+  *Ln = L + hu * (B1 * kl[0] + B3 * kl[2] + B4 * kl[3] + B5 * kl[4] + B6 * kl[5]);
+  double e2 = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double e = hu * (E1 * k1[i] + E3 * k3[i] + E4 * k4[i] + E5 * k5[i] + E6 * k6[i] + E7 * k7[i]);
+    double ay = fabs(y[i]), an = fabs(yn[i]);
+    double sc = par->atol + par->rtol * (ay > an ? ay : an);
+    e2 = e2 + (e / sc) * (e / sc);
+  }
+  double en = sqrt(e2 / N);
+  double el = hu * (E1 * kl[0] + E3 * kl[2] + E4 * kl[3] + E5 * kl[4] + E6 * kl[5] + E7 * kl[6]);
+  double al = fabs(L), anl = fabs(*Ln);
+  double ll = fabs(el) / (par->atol + par->rtol * (al > anl ? al : anl));
+  return ll > en ? ll : en;
+}
+
+int orc_hybrid_run(const orc_net_desc *net, const int32_t *cont, const double *rates,
+                   int64_t rates_ld, const int32_t *x0, int64_t x0_ld, const double *times,
+                   int32_t n_times, int64_t traj0, int64_t n_traj, double *out, int64_t out_ld,
+                   uint64_t *stats, const orc_hybrid_params *par) {
+  if (!net || !cont || !rates || !x0 || !times || !out || !stats || !par) return ORC_E_ARG;
+  if (n_times <= 0 || n_traj < 0 || traj0 < 0 || !(par->rtol > 0.0) || !(par->atol > 0.0) ||
+      par->max_steps < 1)
+    return ORC_E_ARG;
+  for (int s = 0; s < n_times; ++s) {
+    if (!(times[s] >= 0.0) || !isfinite(times[s])) return ORC_E_ARG;
+    if (s > 0 && !(times[s] > times[s - 1])) return ORC_E_ARG;
+  }
+  dnet g;
+  int err = dnet_build(net, &g);
+  if (err) return err;
+  const int N = g.N;
+  double *w = malloc(sizeof(double) * (size_t)N * 12);
+  if (!w) { dnet_free(&g); return ORC_E_NOMEM; }
+  double *y = w, *yn = w + N, *k1 = w + 2 * N, *k2 = w + 3 * N, *k3 = w + 4 * N, *k4 = w + 5 * N,
+         *k5 = w + 6 * N, *k6 = w + 7 * N, *k7 = w + 8 * N, *ys = w + 9 * N, *ye = w + 10 * N,
+         *ke = w + 11 * N;
+  const uint32_t key[2] = {(uint32_t)par->seed, (uint32_t)(par->seed >> 32)};
+  for (int64_t t = 0; t < n_traj; ++t) {
+    const double *c = rates + t;
+    const uint32_t tr = (uint32_t)(traj0 + t);
+    for (int i = 0; i < N; ++i) y[i] = (double)(x0_ld ? x0[(int64_t)i * x0_ld + t] : x0[i]);
+    double tt = 0.0, L = 0.0, xi, u;
+    uint32_t njump = 0;
+    {
+      uint32_t ctr[4] = {tr, 0u, 0u, HYB_STREAM}, o[4];
+      orc_philox4x32_10(ctr, key, o);
+      xi = -log(1.0 - orc_u53(o[0], o[1]));
+      u = orc_u53(o[2], o[3]);
+    }
+    int s = 0;
+    uint64_t acc = 0, rej = 0, status = 0;
+    while (s < n_times && times[s] <= tt) {
+      for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+      s++;
+    }
+    double kl[7];
+    kl[0] = hybrid_rhs(&g, cont, c, rates_ld, y, k1);
+    double d0 = 0.0, d1 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double sc = par->atol + par->rtol * fabs(y[i]);
+      d0 = d0 + (y[i] / sc) * (y[i] / sc);
+      d1 = d1 + (k1[i] / sc) * (k1[i] / sc);
+    }
+    d0 = sqrt(d0 / N);
+    d1 = sqrt(d1 / N);
+    double h = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+    int last_rejected = 0;
+    while (s < n_times) {
+      if (acc + rej >= par->max_steps) { status |= ORC_ST_MAXSTEPS; break; }
+      double delta = times[s] - tt;
+      int clip = !(h < delta);
+      double hu = clip ? delta : h;
+      double Ln;
+      double en = hybrid_step(&g, cont, c, rates_ld, par, hu, y, L, k1, k2, k3, k4, k5, k6, k7,
+                              ys, yn, kl, &Ln);
+      if (!(en <= 1.0)) {
+        double fac = 0.9 * pow(en, -0.2);
+        if (fac < 0.2) fac = 0.2;
+        h = hu * fac;
+        rej++;
+        last_rejected = 1;
+        continue;
+      }
+      double fac = en == 0.0 ? 5.0 : 0.9 * pow(en, -0.2);
+      if (fac > 5.0) fac = 5.0;
+      if (fac < 0.2) fac = 0.2;
+      if (last_rejected && fac > 1.0) fac = 1.0;
+      last_rejected = 0;
+      acc++;
+      if (Ln < xi) {  /* no jump inside the step */
+        memcpy(y, yn, sizeof(double) * N);
+        memcpy(k1, k7, sizeof(double) * N);
+        kl[0] = kl[6];
+        L = Ln;
+        if (clip) tt = times[s];
+        else tt = tt + hu;
+        h = hu * fac;
+        while (s < n_times && times[s] <= tt) {
+          for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+          s++;
+        }
+        continue;
+      }
+      /* The jump lies in (0, hu]: the Illinois variant of regula falsi on the
+       * step length over the bracket [0, hu] of g = L - xi, each trial a full
+       * step from the same start, until |g| <= tol * (1 + xi). */
+      double he = 0.0;
+      memcpy(ye, y, sizeof(double) * N);
+      if (xi - L > 0.0) {
+        double hl = 0.0, gl = L - xi, hr = hu, gr = Ln - xi;
+        int side = 0;
+        for (int r = 0; r < HYB_LOCATE_MAX; ++r) {
+          he = hl - gl * ((hr - hl) / (gr - gl));
+          double kle[7], Le;
+          kle[0] = kl[0];
+          (void)hybrid_step(&g, cont, c, rates_ld, par, he, y, L, k1, k2, k3, k4, k5, k6, ke, ys,
+                            ye, kle, &Le);
+          rej++;
+          double ge = Le - xi;
+          if (fabs(ge) <= HYB_LOCATE_TOL * (1.0 + xi)) break;
+          if (ge < 0.0) {
+            hl = he; gl = ge;
+            if (side < 0) gr = 0.5 * gr;
+            side = -1;
+          } else {
+            hr = he; gr = ge;
+            if (side > 0) gl = 0.5 * gl;
+            side = 1;
+          }
+        }
+      }
+      memcpy(y, ye, sizeof(double) * N);
+      tt = tt + he;
+      h = hu * fac;
+      while (s < n_times && times[s] <= tt) {  /* samples take the pre-jump state */
+        for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+        s++;
+      }
+      /* fire the discrete reaction chosen at the jump state */
+      double a0 = 0.0;
+      for (int j = 0; j < g.M; ++j)
+        if (!cont[j]) a0 = a0 + hybrid_intensity(&g, j, c, rates_ld, y);
+      if (a0 > 0.0) {
+        double r = u * a0, acc_a = 0.0;
+        int pick = -1, last = -1;
+        for (int j = 0; j < g.M && pick < 0; ++j) {
+          if (cont[j]) continue;
+          double a = hybrid_intensity(&g, j, c, rates_ld, y);
+          acc_a = acc_a + a;
+          if (a > 0.0) last = j;
+          if (r < acc_a) pick = j;
+        }
+        if (pick < 0) pick = last;
+        for (int i = 0; i < N; ++i) y[i] = y[i] + (double)g.nu[(size_t)pick * N + i];
+      }
+      njump++;
+      {
+        uint32_t ctr[4] = {tr, njump, 0u, HYB_STREAM}, o[4];
+        orc_philox4x32_10(ctr, key, o);
+        xi = -log(1.0 - orc_u53(o[0], o[1]));
+        u = orc_u53(o[2], o[3]);
+      }
+      L = 0.0;
+      kl[0] = hybrid_rhs(&g, cont, c, rates_ld, y, k1);
+    }
+    while (s < n_times) {
+      for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+      s++;
+    }
+    stats[t * 4 + 0] = acc;
+    stats[t * 4 + 1] = rej;
+    stats[t * 4 + 2] = njump;
     stats[t * 4 + 3] = status;
   }
   free(w);

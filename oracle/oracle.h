@@ -118,6 +118,26 @@ int orc_ode_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
                 int64_t n_traj, double *out, int64_t out_ld, uint64_t *stats,
                 const orc_ode_params *par);
 
+/*
+ * Hybrid stochastic/deterministic sweep (a piecewise-deterministic Markov
+ * process; the construction is described at the top of ode.c).  cont[j] != 0
+ * makes reaction j continuous (part of the flow), 0 discrete (a jump).
+ * Trajectory t of the call has the Philox id traj0 + t.
+ *   out   : out[(s*N + i)*out_ld + t] (double); samples take the pre-jump state
+ *   stats : stats[t*4 + {0: accepted steps, 1: rejected steps and jump-location
+ *           trials, 2: jumps, 3: status}]
+ */
+typedef struct {
+  uint64_t seed;
+  double rtol, atol;
+  uint64_t max_steps;  /* accepted + rejected steps per trajectory (checked per step) */
+} orc_hybrid_params;
+
+int orc_hybrid_run(const orc_net_desc *net, const int32_t *cont, const double *rates,
+                   int64_t rates_ld, const int32_t *x0, int64_t x0_ld, const double *times,
+                   int32_t n_times, int64_t traj0, int64_t n_traj, double *out, int64_t out_ld,
+                   uint64_t *stats, const orc_hybrid_params *par);
+
 #ifdef __cplusplus
 }
 #endif

@@ -332,6 +332,67 @@ int64_t rn_ode_work_doubles(const rn_network *net, int64_t n_traj);
 int rn_ode_sweep(const rn_network *net, const rn_ode_args *args, void *hip_stream);
 
 /*
+ * Hybrid stochastic/deterministic sweep: a piecewise-deterministic Markov
+ * process per trajectory (paper, Methods section: abundant species follow the
+ * mean-field equations, low-amount species keep their fluctuations).
+ * `continuous` (device, [n_reactions] int32, caller-owned) marks each reaction:
+ *  - nonzero: continuous.  Between jumps the state follows the rate equations
+ *    of these reactions, dy/dt = sum_j nu_j c_j h_j(y) with the h of
+ *    rn_ode_sweep, integrated by the same Dormand-Prince 5(4) controller.
+ *  - zero: discrete.  Reaction j jumps (y += nu_j) with intensity
+ *    max(0, c_j h_j(y)), h_j = 1, y_a, y_a*y_b or y_a*(y_a-1)/2.  Jumps come
+ *    when the intensity integral since the previous jump, integrated with the
+ *    flow, reaches an Exp(1) draw (Salis and Kaznessis, J. Chem. Phys. 122,
+ *    054103 (2005)); the crossing is searched by the Illinois regula falsi to
+ *    |L - xi| <= 1e-12 (1 + xi) (at most 30 trials per jump).  The jumping
+ *    reaction is the first discrete j with u * a0_D < a_1 + ... + a_j.
+ * Jump k of trajectory traj_offset + t draws from Philox4x32-10 block
+ * (traj_offset + t, k, 0, 2^31) keyed by `seed`: words 0-1 give
+ * xi = -log(1 - u53), words 2-3 give u.  With every reaction continuous the
+ * results are rn_ode_sweep's; with every reaction discrete, the direct
+ * method's.
+ *  out        device, [n_times][N][out_ld] doubles; samples take the state
+ *             before a jump that lands exactly on them.
+ *  stats      device, [n_traj][4] uint64: accepted steps, rejected steps and
+ *             jump-search trials, jumps, status (2 = max_steps reached; the
+ *             remaining samples repeat the last state).
+ *  work       device scratch of 12 * n_species rows of work_ld doubles
+ *             (rn_hybrid_work_doubles gives the total for work_ld = n_traj).
+ *  rtol, atol finite, > 0; max_steps >= 1 (accepted + rejected, checked
+ *             before each step).
+ * Asynchronous on `hip_stream`; allocates nothing.  Errors: RN_E_INVALID_ARG,
+ * RN_E_DEVICE.
+ */
+typedef struct {
+  int64_t n_traj;
+  int64_t traj_offset;
+  const int32_t *continuous;
+  const double *rates;
+  int64_t rates_ld;
+  const int32_t *x0;
+  int64_t x0_ld;
+  const double *times;
+  int32_t n_times;
+  double *out;
+  int64_t out_ld;
+  uint64_t *stats;
+  double *work;
+  int64_t work_ld;
+  uint64_t seed;
+  double rtol, atol;
+  uint64_t max_steps;
+} rn_hybrid_args;
+
+/* Defaults: rtol 1e-6, atol 1e-6, max_steps 1e7, seed 0, offset 0. */
+void rn_hybrid_args_init(rn_hybrid_args *args);
+
+/* Doubles of workspace rn_hybrid_sweep needs for n_traj trajectories with
+ * work_ld = n_traj (-1 for a null handle or a negative n_traj). */
+int64_t rn_hybrid_work_doubles(const rn_network *net, int64_t n_traj);
+
+int rn_hybrid_sweep(const rn_network *net, const rn_hybrid_args *args, void *hip_stream);
+
+/*
  * Ensemble moments of a sweep's samples, the summary that parameter sweeps,
  * sensitivity analysis and parameter estimation consume (paper, Aims and
  * motivation section).  For every sample s < n_times and species i < n_species,

@@ -626,6 +626,63 @@ int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) 
   return RN_OK;
 }
 
+void rn_hybrid_args_init(rn_hybrid_args* a) {
+  if (!a) return;
+  std::memset(a, 0, sizeof(*a));
+  a->rtol = 1e-6;
+  a->atol = 1e-6;
+  a->max_steps = 10000000ull;
+}
+
+int64_t rn_hybrid_work_doubles(const rn_network* net, int64_t n_traj) {
+  if (!net || n_traj < 0) return -1;
+  return (int64_t)rn::kHybridSlots * net->N * n_traj;
+}
+
+int rn_hybrid_sweep(const rn_network* net, const rn_hybrid_args* a, void* hip_stream) {
+  if (!net || !a) return RN_E_INVALID_ARG;
+  if (a->n_traj < 0 || a->traj_offset < 0 || a->n_times < 1) return RN_E_INVALID_ARG;
+  if (a->traj_offset + a->n_traj > ((int64_t)1 << 32)) return RN_E_INVALID_ARG;
+  if (!(a->rtol > 0.0) || !std::isfinite(a->rtol) || !(a->atol > 0.0) || !std::isfinite(a->atol))
+    return RN_E_INVALID_ARG;
+  if (a->max_steps < 1) return RN_E_INVALID_ARG;
+  if (a->n_traj == 0) return RN_OK;
+  if (!a->continuous || !a->rates || !a->x0 || !a->times || !a->out || !a->stats || !a->work)
+    return RN_E_INVALID_ARG;
+  if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj || a->work_ld < a->n_traj)
+    return RN_E_INVALID_ARG;
+  if (a->x0_ld != 0 && a->x0_ld < a->n_traj) return RN_E_INVALID_ARG;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e);
+  if (dev != net->device) return RN_E_INVALID_ARG;
+  rn::HybridParams p{};
+  p.net = net->dev;
+  p.cont = a->continuous;
+  p.rates = a->rates;
+  p.rates_ld = a->rates_ld;
+  p.x0 = a->x0;
+  p.x0_ld = a->x0_ld;
+  p.times = a->times;
+  p.n_times = a->n_times;
+  p.out = a->out;
+  p.out_ld = a->out_ld;
+  p.stats = a->stats;
+  p.work = a->work;
+  p.work_ld = a->work_ld;
+  p.n_traj = a->n_traj;
+  p.traj_offset = (uint32_t)a->traj_offset;
+  p.key0 = (uint32_t)a->seed;
+  p.key1 = (uint32_t)(a->seed >> 32);
+  p.rtol = a->rtol;
+  p.atol = a->atol;
+  p.max_steps = a->max_steps;
+  e = rn_internal::stage_network(net, (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = rn::launch_hybrid(p, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return device_error(e);
+  return RN_OK;
+}
+
 int rn_moments(const int32_t* out, int64_t out_ld, int32_t n_times, int32_t n_species,
                int64_t n_traj, int64_t* sum_x, uint64_t* sum_x2, void* hip_stream) {
   if (!out || !sum_x || !sum_x2) return RN_E_INVALID_ARG;

@@ -1,0 +1,290 @@
+// rn_hybrid.hip -- hybrid stochastic/deterministic sweep, one lane per
+// parameterization (paper, Methods section: abundant species follow the
+// mean-field equations while low-amount species keep their fluctuations; the
+// process is piecewise-deterministic, Davis 1984).
+//
+// The caller marks each reaction continuous or discrete.  Between jumps the
+// state follows dy/dt = sum over continuous j of nu_j c_j h_j(y) (rate-equation
+// h), integrated by the Dormand-Prince 5(4) pair with the controller of the
+// rate-equation sweep.  The integral L of the discrete intensity
+// a0_D(y) = sum over discrete j of max(0, c_j h_j(y)) (stochastic h, with
+// y(y-1)/2 for a homodimer) rides the same step as one more component.  A jump
+// comes when L reaches an Exp(1) draw xi (the integrated-intensity construction
+// of Salis and Kaznessis, J. Chem. Phys. 122, 054103 (2005)); an accepted step
+// that carries L past xi has its length searched from the same start by the
+// Illinois variant of regula falsi until |L - xi| <= 1e-12 (1 + xi) or 30
+// trials, and the reaction that jumps is the first discrete j with
+// u * a0_D < a_1 + ... + a_j.  Jump k of trajectory tr draws (xi, u) from the
+// Philox block (tr, k, 0, 2^31).
+//
+// Layout: as in the rate-equation sweep, the lane's twelve state vectors live
+// in a caller workspace, trajectory-minor (work[(v * N + i) * work_ld + t]),
+// so every access of a wave covers 64 consecutive doubles; tables and the
+// partition are read at wave-uniform indices through the scalar cache.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rn_device.h"
+#include "rn_dopri.h"
+#include "rn_kernel.h"
+
+namespace rn {
+namespace {
+
+using namespace dopri;
+
+typedef const int32_t __attribute__((address_space(4)))* const_i32_ptr;
+__device__ __forceinline__ int32_t hword(const void* base, int64_t i) {
+  return ((const_i32_ptr)base)[i];
+}
+
+constexpr uint32_t kStreamHybrid = 0x80000000u;
+constexpr uint32_t kHybMaxSteps = 2u;  // status bit, as the other sweeps
+constexpr int kHybWG = 128;
+constexpr int kLocateMax = 30;
+constexpr double kLocateTol = 1e-12;
+
+// Workspace slots: state, candidate, seven stage derivatives, stage argument,
+// and the candidate and last derivative of a jump-search trial.
+enum : int { kY = 0, kYN, kK1, kK2, kK3, kK4, kK5, kK6, kK7, kS, kYE, kKE };
+
+__global__ __launch_bounds__(kHybWG) void hybrid_kernel(const HybridParams p) {
+  const DevNet& g = p.net;
+  const int N = g.N, M = g.M_real;
+  const int64_t tl = (int64_t)blockIdx.x * kHybWG + threadIdx.x;
+  if (tl >= p.n_traj) return;  // lanes are independent: no barrier follows
+  const int64_t ld = p.work_ld;
+  double* const w = p.work + tl;
+  auto V = [&](int slot, int i) -> double& { return w[((int64_t)slot * N + i) * ld]; };
+  const double* const crate = p.rates + tl;
+  const double* __restrict__ times = p.times;
+  const int S = p.n_times;
+  const uint32_t traj = p.traj_offset + (uint32_t)tl;
+
+  auto yv = [&](int slot, int32_t i) -> double { return i < N ? V(slot, i) : 1.0; };
+  // Discrete intensity of reaction j at `slot` (stochastic form, floored at 0).
+  auto intensity = [&](int j, int slot) -> double {
+    const int32_t ia = hword(g.law, 4 * j), ib = hword(g.law, 4 * j + 1);
+    const double ya = yv(slot, ia);
+    double h;
+    if (hword(g.law, 4 * j + 3)) h = 0.5 * (ya * (ya - 1.0));
+    else h = ya * yv(slot, ib);
+    const double a = crate[(int64_t)j * p.rates_ld] * h;
+    return a > 0.0 ? a : 0.0;
+  };
+  // Flow at slot `in` into slot `outv` (each f_i over its continuous reactions
+  // in increasing j); returns a0_D (discrete reactions in increasing j).
+  auto rhs = [&](int in, int outv) -> double {
+    for (int i = 0; i < N; ++i) {
+      double f = 0.0;
+      const int e1 = hword(g.col_ptr, i + 1);
+      for (int e = hword(g.col_ptr, i); e < e1; ++e) {
+        const int j = hword(g.col_ent, 2 * e);
+        if (!hword(p.cont, j)) continue;
+        const int v = hword(g.col_ent, 2 * e + 1);
+        const int32_t ia = hword(g.law, 4 * j), ib = hword(g.law, 4 * j + 1);
+        const double ya = yv(in, ia);
+        double h;
+        if (hword(g.law, 4 * j + 3)) h = 0.5 * (ya * ya);
+        else h = ya * yv(in, ib);
+        const double a = crate[(int64_t)j * p.rates_ld] * h;
+        f = f + (double)v * a;
+      }
+      V(outv, i) = f;
+    }
+    double a0 = 0.0;
+    for (int j = 0; j < M; ++j)
+      if (!hword(p.cont, j)) a0 = a0 + intensity(j, in);
+    return a0;
+  };
+  // One Dormand-Prince step of length hu from (slot y, L) with k1 and kl[0]:
+  // candidate into slot yo, its derivative into slot ko, L' into *Lo; returns
+  // the error norm.
+  auto step = [&](double hu, int y, double L, int k1, int yo, int ko, double* kl,
+                  double* Lo) -> double {
+    for (int i = 0; i < N; ++i) V(kS, i) = V(y, i) + hu * (A21 * V(k1, i));
+    kl[1] = rhs(kS, kK2);
+    for (int i = 0; i < N; ++i) V(kS, i) = V(y, i) + hu * (A31 * V(k1, i) + A32 * V(kK2, i));
+    kl[2] = rhs(kS, kK3);
+    for (int i = 0; i < N; ++i)
+      V(kS, i) = V(y, i) + hu * (A41 * V(k1, i) + A42 * V(kK2, i) + A43 * V(kK3, i));
+    kl[3] = rhs(kS, kK4);
+    for (int i = 0; i < N; ++i)
+      V(kS, i) = V(y, i) + hu * (A51 * V(k1, i) + A52 * V(kK2, i) + A53 * V(kK3, i) +
+                                 A54 * V(kK4, i));
+    kl[4] = rhs(kS, kK5);
+    for (int i = 0; i < N; ++i)
+      V(kS, i) = V(y, i) + hu * (A61 * V(k1, i) + A62 * V(kK2, i) + A63 * V(kK3, i) +
+                                 A64 * V(kK4, i) + A65 * V(kK5, i));
+    kl[5] = rhs(kS, kK6);
+    for (int i = 0; i < N; ++i)
+      V(yo, i) = V(y, i) + hu * (B1 * V(k1, i) + B3 * V(kK3, i) + B4 * V(kK4, i) +
+                                 B5 * V(kK5, i) + B6 * V(kK6, i));
+    kl[6] = rhs(yo, ko);
+    *Lo = L + hu * (B1 * kl[0] + B3 * kl[2] + B4 * kl[3] + B5 * kl[4] + B6 * kl[5]);
+    double e2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double e = hu * (E1 * V(k1, i) + E3 * V(kK3, i) + E4 * V(kK4, i) + E5 * V(kK5, i) +
+                             E6 * V(kK6, i) + E7 * V(ko, i));
+      const double ay = fabs(V(y, i)), an = fabs(V(yo, i));
+      const double sc = p.atol + p.rtol * (ay > an ? ay : an);
+      e2 = e2 + (e / sc) * (e / sc);
+    }
+    const double en = sqrt(e2 / N);
+    const double el =
+        hu * (E1 * kl[0] + E3 * kl[2] + E4 * kl[3] + E5 * kl[4] + E6 * kl[5] + E7 * kl[6]);
+    const double al = fabs(L), anl = fabs(*Lo);
+    const double ll = fabs(el) / (p.atol + p.rtol * (al > anl ? al : anl));
+    return ll > en ? ll : en;
+  };
+  auto record = [&](int yslot, int si) {
+    double* o = p.out + (int64_t)si * N * p.out_ld + tl;
+    for (int i = 0; i < N; ++i) o[(int64_t)i * p.out_ld] = V(yslot, i);
+  };
+  auto draw = [&](uint32_t k, double* xi, double* u) {
+    const dev::Words r = dev::philox10(traj, k, 0u, kStreamHybrid, p.key0, p.key1);
+    *xi = -log(1.0 - dev::u53(r.w0, r.w1));
+    *u = dev::u53(r.w2, r.w3);
+  };
+
+  int ys = kY, yn = kYN, k1 = kK1, k7 = kK7;
+  for (int i = 0; i < N; ++i)
+    V(ys, i) = (double)(p.x0_ld ? p.x0[(int64_t)i * p.x0_ld + tl] : p.x0[i]);
+  double t = 0.0, L = 0.0, xi, u;
+  uint32_t njump = 0;
+  draw(0u, &xi, &u);
+  int s = 0;
+  uint64_t acc = 0, rej = 0;
+  uint32_t status = 0;
+  while (s < S && times[s] <= t) record(ys, s++);
+  double kl[7];
+  kl[0] = rhs(ys, k1);
+  double d0 = 0.0, d1 = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double y = V(ys, i);
+    const double sc = p.atol + p.rtol * fabs(y);
+    const double f = V(k1, i);
+    d0 = d0 + (y / sc) * (y / sc);
+    d1 = d1 + (f / sc) * (f / sc);
+  }
+  d0 = sqrt(d0 / N);
+  d1 = sqrt(d1 / N);
+  double h = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+  bool last_rejected = false;
+  while (s < S) {
+    if (acc + rej >= p.max_steps) {
+      status |= kHybMaxSteps;
+      break;
+    }
+    const double delta = times[s] - t;
+    const bool clip = !(h < delta);
+    const double hu = clip ? delta : h;
+    double Ln;
+    const double en = step(hu, ys, L, k1, yn, k7, kl, &Ln);
+    if (!(en <= 1.0)) {
+      double fac = 0.9 * pow(en, -0.2);
+      if (fac < 0.2) fac = 0.2;
+      h = hu * fac;
+      rej = rej + 1;
+      last_rejected = true;
+      continue;
+    }
+    double fac = en == 0.0 ? 5.0 : 0.9 * pow(en, -0.2);
+    if (fac > 5.0) fac = 5.0;
+    if (fac < 0.2) fac = 0.2;
+    if (last_rejected && fac > 1.0) fac = 1.0;
+    last_rejected = false;
+    acc = acc + 1;
+    if (Ln < xi) {  // no jump inside the step
+      int tmp = ys;
+      ys = yn;
+      yn = tmp;
+      tmp = k1;
+      k1 = k7;
+      k7 = tmp;
+      kl[0] = kl[6];
+      L = Ln;
+      if (clip) t = times[s];
+      else t = t + hu;
+      h = hu * fac;
+      while (s < S && times[s] <= t) record(ys, s++);
+      continue;
+    }
+    // The jump lies in (0, hu]: search the step length (Illinois regula falsi
+    // on g = L - xi over [0, hu]), each trial a full step from the same start.
+    double he = 0.0;
+    int ye = ys;  // a zero-length search leaves the state as it is
+    if (xi - L > 0.0) {
+      double hl = 0.0, gl = L - xi, hr = hu, gr = Ln - xi;
+      int side = 0;
+      for (int r = 0; r < kLocateMax; ++r) {
+        he = hl - gl * ((hr - hl) / (gr - gl));
+        double kle[7], Le;
+        kle[0] = kl[0];
+        (void)step(he, ys, L, k1, kYE, kKE, kle, &Le);
+        ye = kYE;
+        rej = rej + 1;
+        const double ge = Le - xi;
+        if (fabs(ge) <= kLocateTol * (1.0 + xi)) break;
+        if (ge < 0.0) {
+          hl = he;
+          gl = ge;
+          if (side < 0) gr = 0.5 * gr;
+          side = -1;
+        } else {
+          hr = he;
+          gr = ge;
+          if (side > 0) gl = 0.5 * gl;
+          side = 1;
+        }
+      }
+    }
+    if (ye != ys)
+      for (int i = 0; i < N; ++i) V(ys, i) = V(ye, i);
+    t = t + he;
+    h = hu * fac;
+    while (s < S && times[s] <= t) record(ys, s++);  // samples take the pre-jump state
+    double a0 = 0.0;
+    for (int j = 0; j < M; ++j)
+      if (!hword(p.cont, j)) a0 = a0 + intensity(j, ys);
+    if (a0 > 0.0) {
+      const double rr = u * a0;
+      double cum = 0.0;
+      int pick = -1, last = -1;
+      for (int j = 0; j < M && pick < 0; ++j) {
+        if (hword(p.cont, j)) continue;
+        const double a = intensity(j, ys);
+        cum = cum + a;
+        if (a > 0.0) last = j;
+        if (rr < cum) pick = j;
+      }
+      if (pick < 0) pick = last;
+      const int n1 = hword(g.nu_ptr, pick + 1);
+      for (int e = hword(g.nu_ptr, pick); e < n1; ++e) {
+        const int sp = hword(g.nu_ent, 2 * e);
+        V(ys, sp) = V(ys, sp) + (double)hword(g.nu_ent, 2 * e + 1);
+      }
+    }
+    njump = njump + 1;
+    draw(njump, &xi, &u);
+    L = 0.0;
+    kl[0] = rhs(ys, k1);
+  }
+  while (s < S) record(ys, s++);
+  uint64_t* st = p.stats + tl * 4;
+  st[0] = acc;
+  st[1] = rej;
+  st[2] = njump;
+  st[3] = status;
+}
+
+}  // namespace
+
+hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
+  const int64_t blocks = (p.n_traj + kHybWG - 1) / kHybWG;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hybrid_kernel, dim3((unsigned)blocks), dim3(kHybWG), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace rn

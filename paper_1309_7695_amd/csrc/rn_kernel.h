@@ -96,6 +96,31 @@ struct OdeParams {
   uint64_t max_steps;
 };
 
+// Hybrid (piecewise-deterministic) sweep: continuous reactions form a flow
+// integrated like the rate equations, discrete ones jump.
+constexpr int kHybridSlots = 12;  // state vectors per lane in the workspace
+
+struct HybridParams {
+  DevNet net;
+  const int32_t* cont;  // [M_real]: nonzero = continuous
+  const double* rates;
+  int64_t rates_ld;
+  const int32_t* x0;
+  int64_t x0_ld;
+  const double* times;
+  int32_t n_times;
+  double* out;
+  int64_t out_ld;
+  uint64_t* stats;
+  double* work;
+  int64_t work_ld;
+  int64_t n_traj;
+  uint32_t traj_offset;
+  uint32_t key0, key1;
+  double rtol, atol;
+  uint64_t max_steps;
+};
+
 #ifndef __HIPCC_RTC__
 // Launch configuration chosen by the host.
 struct LaunchCfg {
@@ -115,6 +140,7 @@ inline size_t lds_words_per_lane(int N, int M) {
 hipError_t launch_sweep_f64(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_sweep_f32(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
+hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
                           int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream);
 #endif  // __HIPCC_RTC__

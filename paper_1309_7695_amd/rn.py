@@ -33,7 +33,8 @@ EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_netwo
            "rn_server_create", "rn_server_submit", "rn_server_poll", "rn_server_fetch",
            "rn_server_status", "rn_server_free",
            "rn_moments", "rn_ode_args_init",
-           "rn_ode_work_doubles", "rn_ode_sweep", "rn_strerror", "rn_last_device_error"]
+           "rn_ode_work_doubles", "rn_ode_sweep", "rn_hybrid_args_init", "rn_hybrid_work_doubles",
+           "rn_hybrid_sweep", "rn_strerror", "rn_last_device_error"]
 
 
 class NetworkDesc(C.Structure):
@@ -67,6 +68,15 @@ class OdeArgs(C.Structure):
                 ("x0", C.c_void_p), ("x0_ld", C.c_int64), ("times", C.c_void_p),
                 ("n_times", C.c_int32), ("out", C.c_void_p), ("out_ld", C.c_int64),
                 ("stats", C.c_void_p), ("work", C.c_void_p), ("work_ld", C.c_int64),
+                ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
+
+
+class HybridArgs(C.Structure):
+    _fields_ = [("n_traj", C.c_int64), ("traj_offset", C.c_int64), ("continuous", C.c_void_p),
+                ("rates", C.c_void_p), ("rates_ld", C.c_int64), ("x0", C.c_void_p),
+                ("x0_ld", C.c_int64), ("times", C.c_void_p), ("n_times", C.c_int32),
+                ("out", C.c_void_p), ("out_ld", C.c_int64), ("stats", C.c_void_p),
+                ("work", C.c_void_p), ("work_ld", C.c_int64), ("seed", C.c_uint64),
                 ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
 
 
@@ -140,6 +150,12 @@ def lib():
         L.rn_ode_work_doubles.restype = C.c_int64
         L.rn_ode_sweep.argtypes = [C.c_void_p, C.POINTER(OdeArgs), C.c_void_p]
         L.rn_ode_sweep.restype = C.c_int
+        L.rn_hybrid_args_init.argtypes = [C.POINTER(HybridArgs)]
+        L.rn_hybrid_args_init.restype = None
+        L.rn_hybrid_work_doubles.argtypes = [C.c_void_p, C.c_int64]
+        L.rn_hybrid_work_doubles.restype = C.c_int64
+        L.rn_hybrid_sweep.argtypes = [C.c_void_p, C.POINTER(HybridArgs), C.c_void_p]
+        L.rn_hybrid_sweep.restype = C.c_int
         L.rn_strerror.argtypes = [C.c_int]
         L.rn_strerror.restype = C.c_char_p
         L.rn_last_device_error.argtypes = []
@@ -541,5 +557,64 @@ def ode_run(net_desc, rates, x0, times, *, device="cuda", **kw):
                        device=dev)
     ode_sweep(net, torch.from_numpy(rates).to(dev), torch.from_numpy(x0).to(dev),
               torch.from_numpy(times).to(dev), o, s, work, **kw)
+    torch.cuda.synchronize(dev)
+    return o.cpu().numpy(), s.cpu().numpy().view(np.uint64)
+
+
+def hybrid_sweep(net: Network, continuous, rates, x0, times, out, stats, work, *, seed,
+                 rtol=1e-6, atol=1e-6, max_steps=10**7, traj_offset=0, stream=None):
+    """Enqueue ``rn_hybrid_sweep``: ``continuous`` int32 device [M] (nonzero =
+    continuous), ``out`` float64 [S][N][>=T], ``work`` float64 device tensor of at
+    least ``rn_hybrid_work_doubles`` elements; T from ``stats``."""
+    import torch
+
+    T = int(stats.shape[0])
+    if out.dtype != torch.float64 or work.dtype != torch.float64 or not work.is_contiguous():
+        raise TypeError("out and work must be float64 (work contiguous)")
+    if continuous.dtype != torch.int32 or continuous.numel() != net.n_reactions or \
+            not continuous.is_contiguous():
+        raise ValueError("continuous must be a contiguous int32 tensor with one entry per reaction")
+    if work.numel() < lib().rn_hybrid_work_doubles(net.handle, T):
+        raise ValueError("work is too small")
+    if rates.dim() != 2 or rates.stride(1) != 1 or out.dim() != 3 or out.stride(2) != 1 or \
+            out.stride(0) != out.shape[1] * out.stride(1) or out.shape[0] != times.numel():
+        raise ValueError("rates [M][T] and out [S][N][T] need unit trajectory stride")
+    a = HybridArgs()
+    lib().rn_hybrid_args_init(C.byref(a))
+    a.n_traj, a.traj_offset = T, int(traj_offset)
+    a.continuous = continuous.data_ptr()
+    a.rates, a.rates_ld = rates.data_ptr(), rates.stride(0)
+    a.x0, a.x0_ld = x0.data_ptr(), (0 if x0.dim() == 1 else x0.stride(0))
+    a.times, a.n_times = times.data_ptr(), times.numel()
+    a.out, a.out_ld = out.data_ptr(), out.stride(1)
+    a.stats = stats.data_ptr()
+    a.work, a.work_ld = work.data_ptr(), T
+    a.seed = int(seed)
+    a.rtol, a.atol, a.max_steps = float(rtol), float(atol), int(max_steps)
+    if stream is None:
+        stream = torch.cuda.current_stream(rates.device)
+    _check(lib().rn_hybrid_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)),
+           "rn_hybrid_sweep")
+
+
+def hybrid_run(net_desc, continuous, rates, x0, times, *, seed, device="cuda", **kw):
+    """Host-array convenience for :func:`hybrid_sweep`; returns numpy (out, stats)."""
+    import torch
+
+    times = validate_times(times)
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    cont = np.ascontiguousarray(np.asarray(continuous, dtype=bool).astype(np.int32))
+    M, T = rates.shape
+    dev = torch.device(device)
+    net = net_desc if isinstance(net_desc, Network) else Network(net_desc)
+    S, N = len(times), net.n_species
+    o = torch.empty((S, N, T), dtype=torch.float64, device=dev)
+    s = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    work = torch.empty(max(lib().rn_hybrid_work_doubles(net.handle, T), 1), dtype=torch.float64,
+                       device=dev)
+    hybrid_sweep(net, torch.from_numpy(cont).to(dev), torch.from_numpy(rates).to(dev),
+                 torch.from_numpy(x0).to(dev), torch.from_numpy(times).to(dev), o, s, work,
+                 seed=seed, **kw)
     torch.cuda.synchronize(dev)
     return o.cpu().numpy(), s.cpu().numpy().view(np.uint64)

@@ -173,3 +173,15 @@ def test_server_argument_errors_without_device():
     assert L.rn_server_fetch(None, 1, None, None) == rn.RN_E_INVALID_ARG
     assert L.rn_server_submit(None, None, None) == rn.RN_E_INVALID_ARG
     L.rn_server_free(None)
+
+
+def test_hybrid_args_defaults_and_host_checks():
+    L = rn.lib()
+    a = rn.HybridArgs()
+    L.rn_hybrid_args_init(C.byref(a))
+    assert (a.rtol, a.atol, a.max_steps, a.seed, a.traj_offset) == (1e-6, 1e-6, 10**7, 0, 0)
+    assert L.rn_hybrid_work_doubles(None, 10) == -1
+    assert L.rn_hybrid_sweep(None, C.byref(a), None) == rn.RN_E_INVALID_ARG
+    # argument checks that return before any device call (no network needed)
+    a.n_times = 0
+    assert L.rn_hybrid_sweep(None, C.byref(a), None) == rn.RN_E_INVALID_ARG

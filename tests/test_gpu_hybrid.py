@@ -1,0 +1,134 @@
+"""Parity of the hybrid stochastic/deterministic sweep (rn_hybrid_sweep) with
+the FP64 oracle.
+
+Both sides evaluate the same formulas in the same order without fused
+multiply-adds.  Only pow (step control) and log (the Exp(1) jump thresholds)
+go through host and device libraries that may differ in the last bit, which
+moves a step size or a threshold by one ulp.  Consequences:
+- all-discrete sweeps have piecewise-constant integer states, so their samples
+  must agree exactly except where a jump lands within rounding of a sample
+  time (at least 99.9% of trajectories identical);
+- all-continuous sweeps are the rate-equation sweep, bit for bit on the device;
+- mixed sweeps: a shifted threshold or step moves a jump by about rtol in
+  time, and later jumps can amplify that.  Nudging the oracle's own log or pow
+  by one ulp on the 20x40 low-count case below moves one trajectory of 200 by
+  1.5e-5 (1500 rtol) with the 99th percentile at 6 rtol, so the test needs
+  equal jump counts on at least 99% of trajectories, the 99th percentile of
+  |y - y_ref| / (1 + |y_ref|) within 100 rtol and the maximum within 1e4 rtol."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1309_7695_amd import gen, rn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def abundance_partition(net, x0, threshold=100):
+    """Continuous iff every species the reaction touches starts at >= threshold."""
+    cont = []
+    for j in range(net.n_reactions):
+        sp = {s for s, _ in net.reactants[j]} | {s for s, _ in net.products[j]}
+        cont.append(all(int(x0[s]) >= threshold for s in sp))
+    return np.array(cont)
+
+
+@pytest.mark.parametrize("name", ["enzyme", "reversible_dimer"])
+def test_all_discrete_matches_oracle(name):
+    if name == "enzyme":
+        net, c, x0, t_end = gen.enzyme_network(), [0.01, 0.05, 0.05], [20, 60, 0, 0], 30.0
+    else:
+        net, c, x0, t_end = gen.reversible_dimer_network(), [0.02, 0.3], [40, 3], 20.0
+    T = 3000  # several workgroups and a ragged tail
+    rng = np.random.default_rng(8)
+    rates = np.asarray(c, float)[:, None] * gen.log_uniform(rng, 0.5, 2.0, (len(c), T))
+    times = gen.sample_times(t_end, 31)
+    _say(f"case hybrid all-discrete {name}: T={T}")
+    cont = [False] * net.n_reactions
+    out, st = rn.hybrid_run(net, cont, rates, x0, times, seed=17)
+    ref, rst = oracle.hybrid_run(net, cont, rates, x0, times, seed=17, threads=8)
+    same = np.all(out == ref, axis=(0, 1))
+    _say(f"  {same.sum()}/{T} trajectories identical, jumps {int(st[:, 2].sum())}")
+    assert same.mean() >= 0.999
+    assert np.array_equal(st[same, 2], rst[same, 2])
+    assert np.all(st[:, 3] == rst[:, 3])
+
+
+def test_all_continuous_is_the_rate_equation_sweep_on_device():
+    w = gen.synthetic_workload(n_traj=300, t_end=5.0, n_samples=21)
+    _say(f"case hybrid all-continuous: {w.name} T={w.n_traj}")
+    out, st = rn.hybrid_run(w.net, [True] * w.net.n_reactions, w.rates, w.x0, w.times, seed=1)
+    ref, rst = rn.ode_run(w.net, w.rates, w.x0, w.times)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(st[:, :2], rst[:, :2]) and np.all(st[:, 2] == 0)
+
+
+@pytest.mark.parametrize("case", ["enzyme", "synthetic_low_counts"])
+def test_mixed_partition_matches_oracle(case):
+    rtol = 1e-8
+    if case == "enzyme":
+        w = gen.enzyme_workload(n_traj=700)
+        cont = [True, True, False]  # binding in the flow, catalysis as jumps
+        x0 = w.x0
+    else:
+        w = gen.synthetic_workload(n_traj=200, n_species=20, n_reactions=40, t_end=2.0,
+                                   n_samples=11, low_count_frac=0.3, seed=12)
+        cont = abundance_partition(w.net, w.x0)
+        x0 = w.x0
+    _say(f"case hybrid mixed {case}: T={w.n_traj}, {int(np.sum(cont))}/{len(cont)} continuous")
+    out, st = rn.hybrid_run(w.net, cont, w.rates, x0, w.times, seed=23, rtol=rtol, atol=rtol)
+    ref, rst = oracle.hybrid_run(w.net, cont, w.rates, x0, w.times, seed=23, rtol=rtol,
+                                 atol=rtol, threads=8)
+    same_jumps = st[:, 2] == rst[:, 2]
+    err = (np.abs(out - ref) / (1.0 + np.abs(ref))).max(axis=(0, 1))
+    _say(f"  jumps {int(rst[:, 2].sum())}, equal jump counts {same_jumps.mean():.4f}, "
+         f"max rel diff {err[same_jumps].max():.3g}, identical {np.mean(err == 0):.4f}")
+    assert same_jumps.mean() >= 0.99
+    assert np.quantile(err[same_jumps], 0.99) <= 100 * rtol
+    assert err[same_jumps].max() <= 1e4 * rtol
+    assert np.all(st[:, 3] == rst[:, 3])
+
+
+def test_mixed_model_poisson_law_on_device():
+    # A -> 0 continuous (k1), A -> A + B discrete (k2): B(t) is Poisson with
+    # mean k2 A0 (1 - exp(-k1 t)) / k1.
+    net = gen.make_network(2, [([(0, 1)], []), ([(0, 1)], [(0, 1), (1, 1)])])
+    k1, k2, A0, T = 0.5, 0.05, 100, 20000
+    times = gen.sample_times(6.0, 7)
+    rates = np.repeat(np.array([[k1], [k2]]), T, axis=1)
+    _say(f"case hybrid Poisson law: T={T}")
+    out, st = rn.hybrid_run(net, [True, False], rates, [A0, 0], times, seed=29, rtol=1e-8,
+                            atol=1e-8)
+    assert np.allclose(out[:, 0, :], (A0 * np.exp(-k1 * times))[:, None], rtol=1e-6)
+    B = out[:, 1, :]
+    for s in range(1, len(times)):
+        m = k2 * A0 * (1 - math.exp(-k1 * times[s])) / k1
+        assert abs(B[s].mean() - m) < 4 * math.sqrt(m / T), s
+        assert abs(B[s].var() / m - 1) < 4 * math.sqrt(2 / T) + 0.02, s
+
+
+def test_trajectory_offset_and_max_steps():
+    w = gen.enzyme_workload(n_traj=300)
+    cont = [True, True, False]
+    full, sf = rn.hybrid_run(w.net, cont, w.rates, w.x0, w.times, seed=5)
+    part, sp = rn.hybrid_run(w.net, cont, np.ascontiguousarray(w.rates[:, 100:]), w.x0, w.times,
+                             seed=5, traj_offset=100)
+    assert np.array_equal(full[:, :, 100:], part) and np.array_equal(sf[100:], sp)
+    cut, sc = rn.hybrid_run(w.net, cont, w.rates, w.x0, w.times, seed=5, max_steps=7)
+    ref, rsc = oracle.hybrid_run(w.net, cont, w.rates, w.x0, w.times, seed=5, max_steps=7,
+                                 threads=8)
+    assert np.all(sc[:, 3] == 2) and np.all(rsc[:, 3] == 2)
+    assert np.allclose(cut, ref, rtol=1e-9, atol=1e-9)

@@ -89,13 +89,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
-    ap.add_argument("--workload", choices=("synthetic", "batch", "serve", "phases", "copy"),
+    ap.add_argument("--workload",
+                    choices=("synthetic", "batch", "serve", "phases", "copy", "hybrid"),
                     default="synthetic",
                     help="synthetic: the 50x100 sweep of 65,536 trajectories (the headline); "
                          "batch: the uneven batch of 64 networks, batched vs one sweep at a "
                          "time; serve: a Poisson stream of sweep jobs through rn_server; "
                          "phases: per-phase cycle profile of the 50x100 sweep; copy: three 1 GiB "
-                         "device copies (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+                         "device copies (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE); "
+                         "hybrid: the hybrid (PDMP) sweep of the 50x100 network with low counts")
+    ap.add_argument("--hybrid-cpu-sample", type=int, default=32,
+                    help="trajectories the oracle runs for the hybrid cpu_baseline")
     ap.add_argument("--batch-networks", type=int, default=64)
     ap.add_argument("--serve-jobs", type=int, default=1050)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
@@ -182,6 +186,121 @@ def serve_main(args, torch, gen, rn):
         "overloaded": bool(achieved < 0.95 * offered),
         "host_s": host,
     }
+    print(json.dumps(result), flush=True)
+
+
+HYBRID_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "rn_hybrid_hybrid_50x100_traffic.json")
+
+
+def hybrid_main(args, torch, gen, rn):
+    """Hybrid (piecewise-deterministic) sweep: the 50x100 network with a fifth
+    of its species below 10 molecules; reactions touching only species that
+    start at >= 100 molecules are continuous, the others jump.  --n-traj
+    trajectories, t_end 0.5, 11 samples, rtol = atol = 1e-6.  value = Dormand-
+    Prince step evaluations (accepted, rejected and jump-search trials) per
+    second of the timed sweeps."""
+    import hashlib
+
+    dev = torch.device("cuda:0")
+    w = gen.hybrid_workload(n_traj=args.n_traj)
+    cont = gen.abundance_partition(w.net, w.x0)
+    T, M, N, S = w.n_traj, w.net.n_reactions, w.net.n_species, len(w.times)
+    net = rn.Network(w.net)
+    cont_d = torch.from_numpy(cont.astype(np.int32)).to(dev)
+    r = torch.from_numpy(w.rates).to(dev)
+    x = torch.from_numpy(w.x0).to(dev)
+    tm = torch.from_numpy(w.times).to(dev)
+    o = torch.empty((S, N, T), dtype=torch.float64, device=dev)
+    st = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    work = torch.empty(rn.lib().rn_hybrid_work_doubles(net.handle, T), dtype=torch.float64,
+                       device=dev)
+    kw = dict(seed=w.seed, rtol=1e-6, atol=1e-6)
+    print(f"[bench] hybrid {w.name}: T={T} N={N} M={M} S={S}, {int(cont.sum())} continuous "
+          f"reactions", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        rn.hybrid_sweep(net, cont_d, r, x, tm, o, st, work, **kw)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        rn.hybrid_sweep(net, cont_d, r, x, tm, o, st, work, **kw)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    print(f"[bench] timed {args.steps} hybrid sweeps: wall {wall:.3f}s, kernel ms "
+          f"{kern_ms.round(1)}", file=sys.stderr, flush=True)
+    s2 = st.cpu().numpy().view(np.uint64)
+    steps = int(s2[:, 0].sum() + s2[:, 1].sum())
+    jumps = int(s2[:, 2].sum())
+    kern_s = float(np.mean(kern_ms)) / 1000.0
+    result = {
+        "metric": "hybrid (PDMP) sweep: Dormand-Prince step evaluations/sec (1 GPU)",
+        "value": steps * args.steps / wall, "unit": "step-evaluations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} hybrid, low counts", "n_traj": T, "n_species": N,
+                   "n_reactions": M, "continuous_reactions": int(cont.sum()),
+                   "t_end": float(w.times[-1]), "n_samples": S, "rtol": 1e-6, "atol": 1e-6,
+                   "seed": w.seed, "step_evaluations": steps, "accepted": int(s2[:, 0].sum()),
+                   "jumps": jumps, "status_nonzero": int(np.count_nonzero(s2[:, 3]))},
+        "latency_ms": {"p50": float(np.percentile(kern_ms, 50)),
+                       "p99": float(np.percentile(kern_ms, 99))},
+    }
+    # Networks of up to 64 species run one wave per trajectory with the state in
+    # registers, so the kernel is bound by FP64 arithmetic, not HBM.  Algorithmic
+    # FP64 operations of one step evaluation of one trajectory: per species, the
+    # five stage arguments and the candidate (2 per coefficient: 30 + 10) and the
+    # error term (19); per right-hand side (7 per step), 4 for each continuous
+    # (reaction, changed species) entry and 4 for each discrete intensity.
+    nnz_c = 0
+    for j in range(M):
+        if cont[j]:
+            d = {}
+            for s_, k in w.net.products[j]:
+                d[s_] = d.get(s_, 0) + k
+            for s_, k in w.net.reactants[j]:
+                d[s_] = d.get(s_, 0) - k
+            nnz_c += sum(1 for v in d.values() if v != 0)
+    m_d = int(M - cont.sum())
+    flops_per_step = 59 * N + 7 * 4 * (nnz_c + m_d)
+    achieved = flops_per_step * steps / kern_s
+    traffic = None
+    try:
+        rec = json.load(open(HYBRID_TRAFFIC_RECORD))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, "paper_1309_7695_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() == rec["kernel_sources_sha256"] and rec.get("n_traj") == T:
+            traffic = rec["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        traffic = None
+    result["kernel"] = ("hybrid_wave_kernel (rn_hybrid.hip, one wave per trajectory)" if N <= 64
+                        else "hybrid_lane_kernel (rn_hybrid.hip, one lane per trajectory)")
+    result["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": 78.6,
+                          "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": traffic,
+                          "flops_per_step": flops_per_step, "kernel_ms": kern_s * 1e3}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        n = min(args.hybrid_cpu_sample, T)
+        t1 = time.perf_counter()
+        _, ost = oracle.hybrid_run(w.net, cont, w.rates, w.x0, w.times, traj_range=(0, n),
+                                   threads=1, **kw)
+        dt = time.perf_counter() - t1
+        csteps = int(ost[:, 0].sum() + ost[:, 1].sum())
+        cpu = {"value": csteps / dt, "unit": "step-evaluations/s", "cores": 1, "kind": "oracle",
+               "sample": f"trajectories 0..{n - 1} of the same sweep, full horizon, "
+                         f"{csteps} step evaluations in {dt:.1f} s, one thread"}
+    result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 
@@ -356,6 +475,9 @@ def main():
         return
     if args.workload == "copy":
         copy_main(args, torch)
+        return
+    if args.workload == "hybrid":
+        hybrid_main(args, torch, gen, rn)
         return
     dev = torch.device("cuda:0")
     w = gen.synthetic_workload(n_traj=args.n_traj)

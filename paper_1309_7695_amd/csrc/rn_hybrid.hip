@@ -17,10 +17,20 @@
 // u * a0_D < a_1 + ... + a_j.  Jump k of trajectory tr draws (xi, u) from the
 // Philox block (tr, k, 0, 2^31).
 //
-// Layout: as in the rate-equation sweep, the lane's twelve state vectors live
-// in a caller workspace, trajectory-minor (work[(v * N + i) * work_ld + t]),
-// so every access of a wave covers 64 consecutive doubles; tables and the
-// partition are read at wave-uniform indices through the scalar cache.
+// Two kernels compute this.
+//  - Networks of at most 64 species: one wave per trajectory, one lane per
+//    species.  The lane keeps its species' entries of the twelve state vectors
+//    in registers; a stage argument goes through LDS so that every lane can
+//    form its own right-hand side f_i over the reactions that change species
+//    i, and sums over species (error norm, discrete intensity) are wave
+//    reductions.  The rates of the trajectory sit in LDS.  Reductions add in a
+//    butterfly order, not in index order, so results differ from the oracle by
+//    rounding; the jumping reaction is still chosen from index-ordered sums,
+//    as the oracle does.
+//  - Larger networks: one lane per trajectory, its twelve state vectors in a
+//    caller workspace, trajectory-minor (work[(v * N + i) * work_ld + t]), so
+//    every access of a wave covers 64 consecutive doubles; tables and the
+//    partition are read at wave-uniform indices through the scalar cache.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,7 +58,7 @@ constexpr double kLocateTol = 1e-12;
 // and the candidate and last derivative of a jump-search trial.
 enum : int { kY = 0, kYN, kK1, kK2, kK3, kK4, kK5, kK6, kK7, kS, kYE, kKE };
 
-__global__ __launch_bounds__(kHybWG) void hybrid_kernel(const HybridParams p) {
+__global__ __launch_bounds__(kHybWG) void hybrid_lane_kernel(const HybridParams p) {
   const DevNet& g = p.net;
   const int N = g.N, M = g.M_real;
   const int64_t tl = (int64_t)blockIdx.x * kHybWG + threadIdx.x;
@@ -278,12 +288,244 @@ __global__ __launch_bounds__(kHybWG) void hybrid_kernel(const HybridParams p) {
   st[3] = status;
 }
 
+// Sum over the 64 lanes of a wave (xor butterfly: every lane ends with the
+// same bits, since each level adds the same two operands in either order).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off);
+  return v;
+}
+
+constexpr int kWaveWG = 64;
+
+__global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams p) {
+  const DevNet& g = p.net;
+  const int N = g.N, M = g.M_real;
+  const int64_t tl = blockIdx.x;  // one trajectory per wave
+  const int lane = (int)threadIdx.x;
+  const bool own = lane < N;     // the lane carries species `lane`
+  const uint32_t traj = p.traj_offset + (uint32_t)tl;
+  // LDS: stage argument z[64], this trajectory's rates c[M], intensities a[M].
+  extern __shared__ double sh[];
+  double* const z = sh;
+  double* const c = sh + 64;
+  double* const av = c + M;
+  for (int j = lane; j < M; j += kWaveWG) c[j] = p.rates[(int64_t)j * p.rates_ld + tl];
+  const double* __restrict__ times = p.times;
+  const int S = p.n_times;
+  // this lane's species column: reactions that change it, ascending j
+  const int cb = own ? g.col_ptr[lane] : 0, ce = own ? g.col_ptr[lane + 1] : 0;
+
+  auto zv = [&](int32_t i) -> double { return i < N ? z[i] : 1.0; };
+  auto intensity = [&](int j) -> double {  // from z, stochastic form, floored at 0
+    const RateLaw law = g.law[j];
+    const double ya = zv(law.ia);
+    double h;
+    if (law.dimer) h = 0.5 * (ya * (ya - 1.0));
+    else h = ya * zv(law.ib);
+    const double a = c[j] * h;
+    return a > 0.0 ? a : 0.0;
+  };
+  // Publish v as the stage argument and return (f_lane, a0_D) at it.
+  auto rhs = [&](double v, double* a0) -> double {
+    __syncthreads();
+    if (own) z[lane] = v;
+    __syncthreads();
+    double f = 0.0;
+    for (int e = cb; e < ce; ++e) {
+      const int2 ent = g.col_ent[e];
+      const int j = ent.x;
+      if (!p.cont[j]) continue;
+      const RateLaw law = g.law[j];
+      const double ya = zv(law.ia);
+      double h;
+      if (law.dimer) h = 0.5 * (ya * ya);
+      else h = ya * zv(law.ib);
+      f = f + (double)ent.y * (c[j] * h);
+    }
+    double part = 0.0;
+    for (int j = lane; j < M; j += kWaveWG)
+      if (!p.cont[j]) part = part + intensity(j);
+    *a0 = wave_sum(part);
+    return f;
+  };
+  struct Stage {
+    double k2, k3, k4, k5, k6;
+  };
+  // One Dormand-Prince step of length hu from (y, L) with k1, kl[0]: this
+  // lane's candidate and last derivative, L', the error norm.
+  auto step = [&](double hu, double y, double L, double k1, double* kl, Stage& q, double* yo,
+                  double* ko, double* Lo) -> double {
+    q.k2 = rhs(y + hu * (A21 * k1), &kl[1]);
+    q.k3 = rhs(y + hu * (A31 * k1 + A32 * q.k2), &kl[2]);
+    q.k4 = rhs(y + hu * (A41 * k1 + A42 * q.k2 + A43 * q.k3), &kl[3]);
+    q.k5 = rhs(y + hu * (A51 * k1 + A52 * q.k2 + A53 * q.k3 + A54 * q.k4), &kl[4]);
+    q.k6 = rhs(y + hu * (A61 * k1 + A62 * q.k2 + A63 * q.k3 + A64 * q.k4 + A65 * q.k5), &kl[5]);
+    *yo = y + hu * (B1 * k1 + B3 * q.k3 + B4 * q.k4 + B5 * q.k5 + B6 * q.k6);
+    *ko = rhs(*yo, &kl[6]);
+    *Lo = L + hu * (B1 * kl[0] + B3 * kl[2] + B4 * kl[3] + B5 * kl[4] + B6 * kl[5]);
+    double t2 = 0.0;
+    if (own) {
+      const double e = hu * (E1 * k1 + E3 * q.k3 + E4 * q.k4 + E5 * q.k5 + E6 * q.k6 + E7 * *ko);
+      const double ay = fabs(y), an = fabs(*yo);
+      const double sc = p.atol + p.rtol * (ay > an ? ay : an);
+      t2 = (e / sc) * (e / sc);
+    }
+    const double en = sqrt(wave_sum(t2) / N);
+    const double el =
+        hu * (E1 * kl[0] + E3 * kl[2] + E4 * kl[3] + E5 * kl[4] + E6 * kl[5] + E7 * kl[6]);
+    const double al = fabs(L), anl = fabs(*Lo);
+    const double ll = fabs(el) / (p.atol + p.rtol * (al > anl ? al : anl));
+    return ll > en ? ll : en;
+  };
+  auto record = [&](double y, int si) {
+    if (own) p.out[((int64_t)si * N + lane) * p.out_ld + tl] = y;
+  };
+  auto draw = [&](uint32_t k, double* xi, double* u) {
+    const dev::Words r = dev::philox10(traj, k, 0u, kStreamHybrid, p.key0, p.key1);
+    *xi = -log(1.0 - dev::u53(r.w0, r.w1));
+    *u = dev::u53(r.w2, r.w3);
+  };
+
+  double y = own ? (double)(p.x0_ld ? p.x0[(int64_t)lane * p.x0_ld + tl] : p.x0[lane]) : 0.0;
+  double t = 0.0, L = 0.0, xi, u;
+  uint32_t njump = 0;
+  draw(0u, &xi, &u);
+  int s = 0;
+  uint64_t acc = 0, rej = 0;
+  uint32_t status = 0;
+  while (s < S && times[s] <= t) record(y, s++);
+  double kl[7];
+  double k1 = rhs(y, &kl[0]);
+  double d0 = 0.0, d1 = 0.0;
+  if (own) {
+    const double sc = p.atol + p.rtol * fabs(y);
+    d0 = (y / sc) * (y / sc);
+    d1 = (k1 / sc) * (k1 / sc);
+  }
+  d0 = sqrt(wave_sum(d0) / N);
+  d1 = sqrt(wave_sum(d1) / N);
+  double h = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+  bool last_rejected = false;
+  Stage q;
+  while (s < S) {
+    if (acc + rej >= p.max_steps) {
+      status |= kHybMaxSteps;
+      break;
+    }
+    const double delta = times[s] - t;
+    const bool clip = !(h < delta);
+    const double hu = clip ? delta : h;
+    double yn, k7, Ln;
+    const double en = step(hu, y, L, k1, kl, q, &yn, &k7, &Ln);
+    if (!(en <= 1.0)) {
+      double fac = 0.9 * pow(en, -0.2);
+      if (fac < 0.2) fac = 0.2;
+      h = hu * fac;
+      rej = rej + 1;
+      last_rejected = true;
+      continue;
+    }
+    double fac = en == 0.0 ? 5.0 : 0.9 * pow(en, -0.2);
+    if (fac > 5.0) fac = 5.0;
+    if (fac < 0.2) fac = 0.2;
+    if (last_rejected && fac > 1.0) fac = 1.0;
+    last_rejected = false;
+    acc = acc + 1;
+    if (Ln < xi) {  // no jump inside the step
+      y = yn;
+      k1 = k7;
+      kl[0] = kl[6];
+      L = Ln;
+      if (clip) t = times[s];
+      else t = t + hu;
+      h = hu * fac;
+      while (s < S && times[s] <= t) record(y, s++);
+      continue;
+    }
+    // The jump lies in (0, hu]: Illinois regula falsi on the step length.
+    double he = 0.0, ye = y;
+    if (xi - L > 0.0) {
+      double hl = 0.0, gl = L - xi, hr = hu, gr = Ln - xi;
+      int side = 0;
+      for (int r = 0; r < kLocateMax; ++r) {
+        he = hl - gl * ((hr - hl) / (gr - gl));
+        double kle[7], ke, Le;
+        kle[0] = kl[0];
+        (void)step(he, y, L, k1, kle, q, &ye, &ke, &Le);
+        rej = rej + 1;
+        const double ge = Le - xi;
+        if (fabs(ge) <= kLocateTol * (1.0 + xi)) break;
+        if (ge < 0.0) {
+          hl = he;
+          gl = ge;
+          if (side < 0) gr = 0.5 * gr;
+          side = -1;
+        } else {
+          hr = he;
+          gr = ge;
+          if (side > 0) gl = 0.5 * gl;
+          side = 1;
+        }
+      }
+    }
+    y = ye;
+    t = t + he;
+    h = hu * fac;
+    while (s < S && times[s] <= t) record(y, s++);  // samples take the pre-jump state
+    // the jumping reaction, from intensities summed in index order
+    __syncthreads();
+    if (own) z[lane] = y;
+    __syncthreads();
+    for (int j = lane; j < M; j += kWaveWG) av[j] = p.cont[j] ? 0.0 : intensity(j);
+    __syncthreads();
+    double a0 = 0.0;
+    for (int j = 0; j < M; ++j)
+      if (!p.cont[j]) a0 = a0 + av[j];
+    if (a0 > 0.0) {
+      const double rr = u * a0;
+      double cum = 0.0;
+      int pick = -1, last = -1;
+      for (int j = 0; j < M && pick < 0; ++j) {
+        if (p.cont[j]) continue;
+        const double a = av[j];
+        cum = cum + a;
+        if (a > 0.0) last = j;
+        if (rr < cum) pick = j;
+      }
+      if (pick < 0) pick = last;
+      const int n1 = g.nu_ptr[pick + 1];
+      for (int e = g.nu_ptr[pick]; e < n1; ++e) {
+        const int2 ent = g.nu_ent[e];
+        if (ent.x == lane) y = y + (double)ent.y;
+      }
+    }
+    njump = njump + 1;
+    draw(njump, &xi, &u);
+    L = 0.0;
+    k1 = rhs(y, &kl[0]);
+  }
+  while (s < S) record(y, s++);
+  if (lane == 0) {
+    uint64_t* st = p.stats + tl * 4;
+    st[0] = acc;
+    st[1] = rej;
+    st[2] = njump;
+    st[3] = status;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
-  const int64_t blocks = (p.n_traj + kHybWG - 1) / kHybWG;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hybrid_kernel, dim3((unsigned)blocks), dim3(kHybWG), 0, stream, p);
+  if (p.n_traj <= 0) return hipSuccess;
+  const size_t lds = (size_t)(kWaveWG + 2 * (int64_t)p.net.M_real) * sizeof(double);
+  if (p.net.N <= kWaveWG && lds <= 65536) {
+    hipLaunchKernelGGL(hybrid_wave_kernel, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds, stream,
+                       p);
+  } else {
+    const int64_t blocks = (p.n_traj + kHybWG - 1) / kHybWG;
+    hipLaunchKernelGGL(hybrid_lane_kernel, dim3((unsigned)blocks), dim3(kHybWG), 0, stream, p);
+  }
   return hipGetLastError();
 }
 

@@ -261,6 +261,25 @@ def stiff_workload(n_traj=65536, seed=4):
                               low_count_frac=0.2)
 
 
+def abundance_partition(net, x0, threshold=100):
+    """Reaction partition for the hybrid sweep: reaction j is continuous (True)
+    when every species it consumes or produces starts with at least
+    ``threshold`` molecules, else discrete (a rule on the inputs only)."""
+    cont = []
+    for j in range(net.n_reactions):
+        sp = {s for s, _ in net.reactants[j]} | {s for s, _ in net.products[j]}
+        cont.append(all(int(x0[s]) >= threshold for s in sp))
+    return np.array(cont, dtype=bool)
+
+
+def hybrid_workload(n_traj=65536, seed=2, t_end=0.5, n_samples=11):
+    """The 50x100 network of ``synthetic_workload`` with a fifth of its species
+    starting below 10 molecules (the discrete part fires ~1,500 times per unit
+    time per trajectory); pair it with ``abundance_partition``."""
+    return synthetic_workload(n_traj=n_traj, seed=seed, t_end=t_end, n_samples=n_samples,
+                              low_count_frac=0.2)
+
+
 def int_log_uniform(rng, lo, hi, size=None):
     """Integers round(10^U(log10 lo, log10 hi)), clipped to [lo, hi]."""
     return np.clip(np.rint(log_uniform(rng, lo, hi, size)), lo, hi).astype(np.int64)

@@ -296,6 +296,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int kWaveWG = 64;
+constexpr int kLaneEntries = 8;  // continuous reactions of a species held in registers
+constexpr int kLaneDiscrete = 2;  // discrete reactions of a lane held in registers
+constexpr int kZ = 66;            // LDS words of the stage argument (z[N] = 1)
+
+// A rate law packed for registers: ia | ib << 8 | dimer << 16 (species < 256).
+__device__ __forceinline__ int pack_law(const RateLaw& law) {
+  return law.ia | (law.ib << 8) | (law.dimer ? 1 << 16 : 0);
+}
 
 __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams p) {
   const DevNet& g = p.net;
@@ -304,25 +312,59 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
   const int lane = (int)threadIdx.x;
   const bool own = lane < N;     // the lane carries species `lane`
   const uint32_t traj = p.traj_offset + (uint32_t)tl;
-  // LDS: stage argument z[64], this trajectory's rates c[M], intensities a[M].
+  // LDS: stage argument z[kZ] (z[N] = 1, the pseudo-species of lower-order
+  // laws), this trajectory's rates c[M], intensities av[M].
   extern __shared__ double sh[];
   double* const z = sh;
-  double* const c = sh + 64;
+  double* const c = sh + kZ;
   double* const av = c + M;
   for (int j = lane; j < M; j += kWaveWG) c[j] = p.rates[(int64_t)j * p.rates_ld + tl];
+  if (lane == 0) z[N] = 1.0;
   const double* __restrict__ times = p.times;
   const int S = p.n_times;
-  // this lane's species column: reactions that change it, ascending j
+  // This lane's species column (reactions that change it, ascending j): the
+  // first kLaneEntries continuous ones in registers, the rest read from the
+  // tables from index `ovf` on.
   const int cb = own ? g.col_ptr[lane] : 0, ce = own ? g.col_ptr[lane + 1] : 0;
+  double ec[kLaneEntries];
+  int el[kLaneEntries], ev[kLaneEntries];
+  int cnt = 0, ovf = ce;
+  for (int e = cb; e < ce; ++e) {
+    const int2 ent = g.col_ent[e];
+    if (!p.cont[ent.x]) continue;
+    if (cnt == kLaneEntries) {
+      ovf = e;
+      break;
+    }
+    const double cj = p.rates[(int64_t)ent.x * p.rates_ld + tl];
+    const int pl = pack_law(g.law[ent.x]);
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k)
+      if (k == cnt) {
+        ec[k] = cj;
+        el[k] = pl;
+        ev[k] = ent.y;
+      }
+    ++cnt;
+  }
+  // This lane's discrete reactions j = lane + 64 d: the first kLaneDiscrete in
+  // registers (law < 0: not discrete or past M), the rest from the tables.
+  double dc[kLaneDiscrete];
+  int dl[kLaneDiscrete];
+#pragma unroll
+  for (int d = 0; d < kLaneDiscrete; ++d) {
+    const int j = lane + kWaveWG * d;
+    const bool disc = j < M && !p.cont[j];
+    dc[d] = disc ? p.rates[(int64_t)j * p.rates_ld + tl] : 0.0;
+    dl[d] = disc ? pack_law(g.law[j]) : -1;
+  }
 
-  auto zv = [&](int32_t i) -> double { return i < N ? z[i] : 1.0; };
-  auto intensity = [&](int j) -> double {  // from z, stochastic form, floored at 0
-    const RateLaw law = g.law[j];
-    const double ya = zv(law.ia);
-    double h;
-    if (law.dimer) h = 0.5 * (ya * (ya - 1.0));
-    else h = ya * zv(law.ib);
-    const double a = c[j] * h;
+  auto h_stoch = [&](int pl) -> double {  // stochastic mass-action factor at z
+    const double ya = z[pl & 0xff];
+    return (pl >> 16) ? 0.5 * (ya * (ya - 1.0)) : ya * z[(pl >> 8) & 0xff];
+  };
+  auto intensity = [&](int j) -> double {  // from z and the tables, floored at 0
+    const double a = c[j] * h_stoch(pack_law(g.law[j]));
     return a > 0.0 ? a : 0.0;
   };
   // Publish v as the stage argument and return (f_lane, a0_D) at it.
@@ -331,19 +373,33 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
     if (own) z[lane] = v;
     __syncthreads();
     double f = 0.0;
-    for (int e = cb; e < ce; ++e) {
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k) {
+      if (k < cnt) {
+        const int pl = el[k];
+        const double ya = z[pl & 0xff];
+        const double h = (pl >> 16) ? 0.5 * (ya * ya) : ya * z[(pl >> 8) & 0xff];
+        f = f + (double)ev[k] * (ec[k] * h);
+      }
+    }
+    for (int e = ovf; e < ce; ++e) {
       const int2 ent = g.col_ent[e];
       const int j = ent.x;
       if (!p.cont[j]) continue;
-      const RateLaw law = g.law[j];
-      const double ya = zv(law.ia);
-      double h;
-      if (law.dimer) h = 0.5 * (ya * ya);
-      else h = ya * zv(law.ib);
+      const int pl = pack_law(g.law[j]);
+      const double ya = z[pl & 0xff];
+      const double h = (pl >> 16) ? 0.5 * (ya * ya) : ya * z[(pl >> 8) & 0xff];
       f = f + (double)ent.y * (c[j] * h);
     }
     double part = 0.0;
-    for (int j = lane; j < M; j += kWaveWG)
+#pragma unroll
+    for (int d = 0; d < kLaneDiscrete; ++d) {
+      if (dl[d] >= 0) {
+        const double a = dc[d] * h_stoch(dl[d]);
+        part = part + (a > 0.0 ? a : 0.0);
+      }
+    }
+    for (int j = lane + kWaveWG * kLaneDiscrete; j < M; j += kWaveWG)
       if (!p.cont[j]) part = part + intensity(j);
     *a0 = wave_sum(part);
     return f;
@@ -407,70 +463,92 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
   double h = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
   bool last_rejected = false;
   Stage q;
+  // One step evaluation per iteration: an ordinary step, or a trial of the
+  // jump search (Illinois regula falsi on the length of the step that carried
+  // L past xi, from that step's start), so the step is inlined once.
+  bool searching = false;
+  double hl = 0.0, gl = 0.0, hr = 0.0, gr = 0.0, hnext = 0.0;
+  int side = 0, trials = 0;
   while (s < S) {
-    if (acc + rej >= p.max_steps) {
-      status |= kHybMaxSteps;
-      break;
+    double hu = 0.0;
+    bool clip = false;
+    if (!searching) {
+      if (acc + rej >= p.max_steps) {
+        status |= kHybMaxSteps;
+        break;
+      }
+      const double delta = times[s] - t;
+      clip = !(h < delta);
+      hu = clip ? delta : h;
+    } else {
+      hu = hl - gl * ((hr - hl) / (gr - gl));
     }
-    const double delta = times[s] - t;
-    const bool clip = !(h < delta);
-    const double hu = clip ? delta : h;
     double yn, k7, Ln;
     const double en = step(hu, y, L, k1, kl, q, &yn, &k7, &Ln);
-    if (!(en <= 1.0)) {
-      double fac = 0.9 * pow(en, -0.2);
-      if (fac < 0.2) fac = 0.2;
-      h = hu * fac;
-      rej = rej + 1;
-      last_rejected = true;
-      continue;
-    }
-    double fac = en == 0.0 ? 5.0 : 0.9 * pow(en, -0.2);
-    if (fac > 5.0) fac = 5.0;
-    if (fac < 0.2) fac = 0.2;
-    if (last_rejected && fac > 1.0) fac = 1.0;
-    last_rejected = false;
-    acc = acc + 1;
-    if (Ln < xi) {  // no jump inside the step
-      y = yn;
-      k1 = k7;
-      kl[0] = kl[6];
-      L = Ln;
-      if (clip) t = times[s];
-      else t = t + hu;
-      h = hu * fac;
-      while (s < S && times[s] <= t) record(y, s++);
-      continue;
-    }
-    // The jump lies in (0, hu]: Illinois regula falsi on the step length.
     double he = 0.0, ye = y;
-    if (xi - L > 0.0) {
-      double hl = 0.0, gl = L - xi, hr = hu, gr = Ln - xi;
-      int side = 0;
-      for (int r = 0; r < kLocateMax; ++r) {
-        he = hl - gl * ((hr - hl) / (gr - gl));
-        double kle[7], ke, Le;
-        kle[0] = kl[0];
-        (void)step(he, y, L, k1, kle, q, &ye, &ke, &Le);
+    if (!searching) {
+      if (!(en <= 1.0)) {
+        double fac = 0.9 * pow(en, -0.2);
+        if (fac < 0.2) fac = 0.2;
+        h = hu * fac;
         rej = rej + 1;
-        const double ge = Le - xi;
-        if (fabs(ge) <= kLocateTol * (1.0 + xi)) break;
+        last_rejected = true;
+        continue;
+      }
+      double fac = en == 0.0 ? 5.0 : 0.9 * pow(en, -0.2);
+      if (fac > 5.0) fac = 5.0;
+      if (fac < 0.2) fac = 0.2;
+      if (last_rejected && fac > 1.0) fac = 1.0;
+      last_rejected = false;
+      acc = acc + 1;
+      if (Ln < xi) {  // no jump inside the step
+        y = yn;
+        k1 = k7;
+        kl[0] = kl[6];
+        L = Ln;
+        if (clip) t = times[s];
+        else t = t + hu;
+        h = hu * fac;
+        while (s < S && times[s] <= t) record(y, s++);
+        continue;
+      }
+      hnext = hu * fac;
+      if (xi - L > 0.0) {  // the jump lies in (0, hu]: search its length
+        searching = true;
+        hl = 0.0;
+        gl = L - xi;
+        hr = hu;
+        gr = Ln - xi;
+        side = 0;
+        trials = 0;
+        continue;
+      }
+      // xi - L <= 0: the jump is at the start of the step
+    } else {
+      rej = rej + 1;
+      trials = trials + 1;
+      const double ge = Ln - xi;
+      if (!(fabs(ge) <= kLocateTol * (1.0 + xi)) && trials < kLocateMax) {
         if (ge < 0.0) {
-          hl = he;
+          hl = hu;
           gl = ge;
           if (side < 0) gr = 0.5 * gr;
           side = -1;
         } else {
-          hr = he;
+          hr = hu;
           gr = ge;
           if (side > 0) gl = 0.5 * gl;
           side = 1;
         }
+        continue;
       }
+      searching = false;
+      he = hu;
+      ye = yn;
     }
     y = ye;
     t = t + he;
-    h = hu * fac;
+    h = hnext;
     while (s < S && times[s] <= t) record(y, s++);  // samples take the pre-jump state
     // the jumping reaction, from intensities summed in index order
     __syncthreads();
@@ -518,7 +596,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
 
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
   if (p.n_traj <= 0) return hipSuccess;
-  const size_t lds = (size_t)(kWaveWG + 2 * (int64_t)p.net.M_real) * sizeof(double);
+  const size_t lds = (size_t)(kZ + 2 * (int64_t)p.net.M_real) * sizeof(double);
   if (p.net.N <= kWaveWG && lds <= 65536) {
     hipLaunchKernelGGL(hybrid_wave_kernel, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds, stream,
                        p);

@@ -320,7 +320,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kWaveWG = 64;
 constexpr int kLaneEntries = 8;  // continuous reactions of a species held in registers
-constexpr int kLaneDiscrete = 2;  // discrete reactions of a lane held in registers
+constexpr int kLaneSlots = 2;     // reactions of a lane (j = lane + 64 d) held in registers
 constexpr int kZ = 66;            // LDS words of the stage argument (z[N] = 1)
 
 // A rate law packed for registers: ia | ib << 8 | dimer << 16 (species < 256).
@@ -336,21 +336,36 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
   const bool own = lane < N;     // the lane carries species `lane`
   const uint32_t traj = p.traj_offset + (uint32_t)tl;
   // LDS: stage argument z[kZ] (z[N] = 1, the pseudo-species of lower-order
-  // laws), this trajectory's rates c[M], intensities av[M].
+  // laws), this trajectory's rates c[M], intensities av[M] at a jump, and the
+  // continuous reactions' rates ac[M] at the stage argument.
   extern __shared__ double sh[];
   double* const z = sh;
   double* const c = sh + kZ;
   double* const av = c + M;
+  double* const ac = av + M;
   for (int j = lane; j < M; j += kWaveWG) c[j] = p.rates[(int64_t)j * p.rates_ld + tl];
   if (lane == 0) z[N] = 1.0;
   const double* __restrict__ times = p.times;
   const int S = p.n_times;
+  // Reaction slots of this lane: j = lane + 64 d for d < kLaneSlots, with
+  // their packed law and rate in registers (law < 0: past M); continuous ones
+  // publish a_j to LDS, discrete ones add to the lane's share of a0_D.
+  double sc_[kLaneSlots];
+  int sl[kLaneSlots];
+  bool scont[kLaneSlots];
+#pragma unroll
+  for (int d = 0; d < kLaneSlots; ++d) {
+    const int j = lane + kWaveWG * d;
+    const bool in = j < M;
+    sc_[d] = in ? p.rates[(int64_t)j * p.rates_ld + tl] : 0.0;
+    sl[d] = in ? pack_law(g.law[j]) : -1;
+    scont[d] = in && p.cont[j] != 0;
+  }
   // This lane's species column (reactions that change it, ascending j): the
-  // first kLaneEntries continuous ones in registers, the rest read from the
-  // tables from index `ovf` on.
+  // first kLaneEntries continuous ones as (j, nu) in registers, the rest read
+  // from the tables from index `ovf` on.
   const int cb = own ? g.col_ptr[lane] : 0, ce = own ? g.col_ptr[lane + 1] : 0;
-  double ec[kLaneEntries];
-  int el[kLaneEntries], ev[kLaneEntries];
+  int ej[kLaneEntries], ev[kLaneEntries];
   int cnt = 0, ovf = ce;
   for (int e = cb; e < ce; ++e) {
     const int2 ent = g.col_ent[e];
@@ -359,71 +374,59 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
       ovf = e;
       break;
     }
-    const double cj = p.rates[(int64_t)ent.x * p.rates_ld + tl];
-    const int pl = pack_law(g.law[ent.x]);
 #pragma unroll
     for (int k = 0; k < kLaneEntries; ++k)
       if (k == cnt) {
-        ec[k] = cj;
-        el[k] = pl;
+        ej[k] = ent.x;
         ev[k] = ent.y;
       }
     ++cnt;
-  }
-  // This lane's discrete reactions j = lane + 64 d: the first kLaneDiscrete in
-  // registers (law < 0: not discrete or past M), the rest from the tables.
-  double dc[kLaneDiscrete];
-  int dl[kLaneDiscrete];
-#pragma unroll
-  for (int d = 0; d < kLaneDiscrete; ++d) {
-    const int j = lane + kWaveWG * d;
-    const bool disc = j < M && !p.cont[j];
-    dc[d] = disc ? p.rates[(int64_t)j * p.rates_ld + tl] : 0.0;
-    dl[d] = disc ? pack_law(g.law[j]) : -1;
   }
 
   auto h_stoch = [&](int pl) -> double {  // stochastic mass-action factor at z
     const double ya = z[pl & 0xff];
     return (pl >> 16) ? 0.5 * (ya * (ya - 1.0)) : ya * z[(pl >> 8) & 0xff];
   };
+  auto h_det = [&](int pl) -> double {  // rate-equation factor at z
+    const double ya = z[pl & 0xff];
+    return (pl >> 16) ? 0.5 * (ya * ya) : ya * z[(pl >> 8) & 0xff];
+  };
   auto intensity = [&](int j) -> double {  // from z and the tables, floored at 0
     const double a = c[j] * h_stoch(pack_law(g.law[j]));
     return a > 0.0 ? a : 0.0;
   };
-  // Publish v as the stage argument and return (f_lane, a0_D) at it.
+  // Publish v as the stage argument and return (f_lane, a0_D) at it: every
+  // reaction's rate is formed once (continuous ones through LDS, ac[j]), then
+  // each species lane sums nu_ij a_j over its column in increasing j.
   auto rhs = [&](double v, double* a0) -> double {
     __syncthreads();
     if (own) z[lane] = v;
     __syncthreads();
-    double f = 0.0;
-#pragma unroll
-    for (int k = 0; k < kLaneEntries; ++k) {
-      if (k < cnt) {
-        const int pl = el[k];
-        const double ya = z[pl & 0xff];
-        const double h = (pl >> 16) ? 0.5 * (ya * ya) : ya * z[(pl >> 8) & 0xff];
-        f = f + (double)ev[k] * (ec[k] * h);
-      }
-    }
-    for (int e = ovf; e < ce; ++e) {
-      const int2 ent = g.col_ent[e];
-      const int j = ent.x;
-      if (!p.cont[j]) continue;
-      const int pl = pack_law(g.law[j]);
-      const double ya = z[pl & 0xff];
-      const double h = (pl >> 16) ? 0.5 * (ya * ya) : ya * z[(pl >> 8) & 0xff];
-      f = f + (double)ent.y * (c[j] * h);
-    }
     double part = 0.0;
 #pragma unroll
-    for (int d = 0; d < kLaneDiscrete; ++d) {
-      if (dl[d] >= 0) {
-        const double a = dc[d] * h_stoch(dl[d]);
-        part = part + (a > 0.0 ? a : 0.0);
+    for (int d = 0; d < kLaneSlots; ++d) {
+      if (sl[d] >= 0) {
+        if (scont[d]) {
+          ac[lane + kWaveWG * d] = sc_[d] * h_det(sl[d]);
+        } else {
+          const double a = sc_[d] * h_stoch(sl[d]);
+          part = part + (a > 0.0 ? a : 0.0);
+        }
       }
     }
-    for (int j = lane + kWaveWG * kLaneDiscrete; j < M; j += kWaveWG)
-      if (!p.cont[j]) part = part + intensity(j);
+    for (int j = lane + kWaveWG * kLaneSlots; j < M; j += kWaveWG) {
+      if (p.cont[j]) ac[j] = c[j] * h_det(pack_law(g.law[j]));
+      else part = part + intensity(j);
+    }
+    __syncthreads();
+    double f = 0.0;
+#pragma unroll
+    for (int k = 0; k < kLaneEntries; ++k)
+      if (k < cnt) f = f + (double)ev[k] * ac[ej[k]];
+    for (int e = ovf; e < ce; ++e) {
+      const int2 ent = g.col_ent[e];
+      if (p.cont[ent.x]) f = f + (double)ent.y * ac[ent.x];
+    }
     *a0 = wave_sum(part);
     return f;
   };
@@ -619,7 +622,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
 
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
   if (p.n_traj <= 0) return hipSuccess;
-  const size_t lds = (size_t)(kZ + 2 * (int64_t)p.net.M_real) * sizeof(double);
+  const size_t lds = (size_t)(kZ + 3 * (int64_t)p.net.M_real) * sizeof(double);
   if (p.net.N <= kWaveWG && lds <= 65536) {
     hipLaunchKernelGGL(hybrid_wave_kernel, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds, stream,
                        p);

@@ -90,16 +90,21 @@ def parse():
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
     ap.add_argument("--workload",
-                    choices=("synthetic", "batch", "serve", "phases", "copy", "hybrid"),
+                    choices=("synthetic", "batch", "serve", "phases", "copy", "hybrid", "ode",
+                             "moments"),
                     default="synthetic",
                     help="synthetic: the 50x100 sweep of 65,536 trajectories (the headline); "
                          "batch: the uneven batch of 64 networks, batched vs one sweep at a "
                          "time; serve: a Poisson stream of sweep jobs through rn_server; "
                          "phases: per-phase cycle profile of the 50x100 sweep; copy: three 1 GiB "
                          "device copies (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE); "
-                         "hybrid: the hybrid (PDMP) sweep of the 50x100 network with low counts")
+                         "hybrid: the hybrid (PDMP) sweep of the 50x100 network with low counts; "
+                         "ode: the rate-equation sweep of the 50x100 workload; moments: the "
+                         "ensemble-moment reduction of a 50x100 sample array")
     ap.add_argument("--hybrid-cpu-sample", type=int, default=32,
                     help="trajectories the oracle runs for the hybrid cpu_baseline")
+    ap.add_argument("--ode-cpu-sample", type=int, default=8,
+                    help="trajectories the oracle runs for the rate-equation cpu_baseline")
     ap.add_argument("--batch-networks", type=int, default=64)
     ap.add_argument("--serve-jobs", type=int, default=1050)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
@@ -304,6 +309,133 @@ def hybrid_main(args, torch, gen, rn):
     print(json.dumps(result), flush=True)
 
 
+def _timed(torch, dev, args, launch, label):
+    for i in range(args.warmup):
+        launch()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        launch()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    print(f"[bench] timed {args.steps} {label}: wall {wall:.3f}s, kernel ms {kern_ms.round(2)}",
+          file=sys.stderr, flush=True)
+    return wall, kern_ms
+
+
+def ode_main(args, torch, gen, rn):
+    """Rate-equation (ODE) sweep of the headline workload: the 50x100 network,
+    --n-traj trajectories with their own rates, t_end 50, 200 samples,
+    rtol = atol = 1e-6.  value = Dormand-Prince step evaluations (accepted and
+    rejected) per second."""
+    dev = torch.device("cuda:0")
+    w = gen.synthetic_workload(n_traj=args.n_traj)
+    T, M, N, S = w.n_traj, w.net.n_reactions, w.net.n_species, len(w.times)
+    net = rn.Network(w.net)
+    r = torch.from_numpy(w.rates).to(dev)
+    x = torch.from_numpy(w.x0).to(dev)
+    tm = torch.from_numpy(w.times).to(dev)
+    o = torch.empty((S, N, T), dtype=torch.float64, device=dev)
+    st = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    work = torch.empty(rn.lib().rn_ode_work_doubles(net.handle, T), dtype=torch.float64,
+                       device=dev)
+    print(f"[bench] ode {w.name}: T={T} N={N} M={M} S={S}", file=sys.stderr, flush=True)
+    wall, kern_ms = _timed(torch, dev, args,
+                           lambda: rn.ode_sweep(net, r, x, tm, o, st, work), "ode sweeps")
+    s2 = st.cpu().numpy().view(np.uint64)
+    steps = int(s2[:, 0].sum() + s2[:, 1].sum())
+    kern_s = float(np.mean(kern_ms)) / 1000.0
+    # Algorithmic FP64 operations of one step evaluation of one trajectory (the
+    # count of the hybrid sweep with every reaction continuous): 59 per species
+    # and 4 per (reaction, changed species) entry for each of the 7 right-hand
+    # sides.
+    nnz = 0
+    for j in range(M):
+        d = {}
+        for s_, k in w.net.products[j]:
+            d[s_] = d.get(s_, 0) + k
+        for s_, k in w.net.reactants[j]:
+            d[s_] = d.get(s_, 0) - k
+        nnz += sum(1 for v in d.values() if v != 0)
+    flops_per_step = 59 * N + 7 * 4 * nnz
+    achieved = flops_per_step * steps / kern_s
+    result = {
+        "metric": "rate-equation sweep: Dormand-Prince step evaluations/sec (1 GPU)",
+        "value": steps * args.steps / wall, "unit": "step-evaluations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} rate equations", "n_traj": T, "n_species": N,
+                   "n_reactions": M, "t_end": float(w.times[-1]), "n_samples": S,
+                   "rtol": 1e-6, "atol": 1e-6, "step_evaluations": steps,
+                   "accepted": int(s2[:, 0].sum()),
+                   "status_nonzero": int(np.count_nonzero(s2[:, 3]))},
+        "kernel": ("hybrid_wave_kernel<ode> (rn_hybrid.hip, one wave per trajectory)" if N <= 64
+                   else "ode_kernel (rn_ode.hip, one lane per trajectory)"),
+        "latency_ms": {"p50": float(np.percentile(kern_ms, 50)),
+                       "p99": float(np.percentile(kern_ms, 99))},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": None,
+                     "flops_per_step": flops_per_step, "kernel_ms": kern_s * 1e3},
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        n = min(args.ode_cpu_sample, T)
+        t1 = time.perf_counter()
+        _, ost = oracle.ode_run(w.net, w.rates, w.x0, w.times, traj_range=(0, n), threads=1)
+        dt = time.perf_counter() - t1
+        csteps = int(ost[:, 0].sum() + ost[:, 1].sum())
+        cpu = {"value": csteps / dt, "unit": "step-evaluations/s", "cores": 1, "kind": "oracle",
+               "sample": f"trajectories 0..{n - 1} of the same sweep, full horizon, "
+                         f"{csteps} step evaluations in {dt:.1f} s, one thread"}
+    result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
+
+
+def moments_main(args, torch, gen, rn):
+    """Ensemble moments (rn_moments) of a sample array of the headline shape:
+    200 samples x 50 species x --n-traj trajectories of int32 counts in
+    [0, 1000].  HBM-bound: value = bytes of samples read per second."""
+    dev = torch.device("cuda:0")
+    S, N, T = 200, 50, args.n_traj
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    out = torch.randint(0, 1001, (S, N, T), dtype=torch.int32, device=dev, generator=g)
+    sx = torch.empty((S, N), dtype=torch.int64, device=dev)
+    sx2 = torch.empty((S, N, 2), dtype=torch.int64, device=dev)
+    wall, kern_ms = _timed(torch, dev, args,
+                           lambda: rn.moments(out, sum_x=sx, sum_x2=sx2), "moment reductions")
+    ref = out.to(torch.int64).sum(dim=2)
+    assert torch.equal(ref, sx), "moment sums differ from torch's"
+    kern_s = float(np.mean(kern_ms)) / 1000.0
+    nbytes = S * N * T * 4 + S * N * 24
+    result = {
+        "metric": "ensemble-moment reduction: sample bytes/sec (1 GPU)",
+        "value": nbytes * args.steps / wall, "unit": "B/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32/int64/u128", "data": "synthetic",
+        "config": {"workload": "moments of [200][50][T] int32 samples", "n_traj": T},
+        "kernel": "moments_kernel (rn_moments.hip)",
+        "latency_ms": {"p50": float(np.percentile(kern_ms, 50)),
+                       "p99": float(np.percentile(kern_ms, 99))},
+        "roofline": {"bound": "hbm", "achieved": nbytes / kern_s / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": nbytes / kern_s / 8e12, "traffic": None,
+                     "kernel_ms": kern_s * 1e3},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def copy_main(args, torch):
     """Three device copies of 1 GiB (torch's copy kernel): the reference the
     FETCH_SIZE and WRITE_SIZE counters are scaled by."""
@@ -478,6 +610,12 @@ def main():
         return
     if args.workload == "hybrid":
         hybrid_main(args, torch, gen, rn)
+        return
+    if args.workload == "ode":
+        ode_main(args, torch, gen, rn)
+        return
+    if args.workload == "moments":
+        moments_main(args, torch, gen, rn)
         return
     dev = torch.device("cuda:0")
     w = gen.synthetic_workload(n_traj=args.n_traj)

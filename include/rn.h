@@ -301,6 +301,9 @@ void rn_server_free(rn_server *s);
  *  work       device scratch of 10 * n_species rows of work_ld doubles
  *             (work_ld >= n_traj; rn_ode_work_doubles gives the total for
  *             work_ld = n_traj), caller-owned; its contents on entry are ignored.
+ *             Networks of up to 64 species run one wave per trajectory with
+ *             the state in registers and leave it untouched (their sums over
+ *             species then add in a butterfly order, not in species order).
  *  rtol, atol finite, > 0; max_steps >= 1.
  * Asynchronous on `hip_stream`; allocates nothing.  Errors: RN_E_INVALID_ARG,
  * RN_E_DEVICE.

@@ -398,6 +398,12 @@ static hipFunction_t network_kernel(const rn_network* net, int32_t precision, in
               : rn::jit_kernel_nowait(net->jit_consts, prec, wg);
 }
 
+namespace rn {
+// rn_hybrid.hip: the rate-equation sweep on the wave-per-trajectory kernel;
+// false (nothing launched) when the network does not fit it.
+bool launch_ode_wave(const HybridParams& p, hipStream_t stream, hipError_t* err);
+}  // namespace rn
+
 namespace rn_internal {
 
 // Make the network's device tables valid for work enqueued next on `stream`.
@@ -621,7 +627,26 @@ int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) 
   p.atol = a->atol;
   p.max_steps = a->max_steps;
   e = rn_internal::stage_network(net, (hipStream_t)hip_stream);
-  if (e == hipSuccess) e = rn::launch_ode(p, (hipStream_t)hip_stream);
+  if (e == hipSuccess) {
+    // networks of up to 64 species: one wave per trajectory, state in registers
+    rn::HybridParams hp{};
+    hp.net = p.net;
+    hp.rates = p.rates;
+    hp.rates_ld = p.rates_ld;
+    hp.x0 = p.x0;
+    hp.x0_ld = p.x0_ld;
+    hp.times = p.times;
+    hp.n_times = p.n_times;
+    hp.out = p.out;
+    hp.out_ld = p.out_ld;
+    hp.stats = p.stats;
+    hp.n_traj = p.n_traj;
+    hp.rtol = p.rtol;
+    hp.atol = p.atol;
+    hp.max_steps = p.max_steps;
+    if (!rn::launch_ode_wave(hp, (hipStream_t)hip_stream, &e))
+      e = rn::launch_ode(p, (hipStream_t)hip_stream);
+  }
   if (e != hipSuccess) return device_error(e);
   return RN_OK;
 }

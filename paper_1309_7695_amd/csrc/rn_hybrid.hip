@@ -328,6 +328,9 @@ __device__ __forceinline__ int pack_law(const RateLaw& law) {
   return law.ia | (law.ib << 8) | (law.dimer ? 1 << 16 : 0);
 }
 
+// kOde: every reaction continuous and p.cont unused, i.e. the reaction-rate
+// equations of rn_ode_sweep (no draws, no jumps).
+template <bool kOde>
 __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams p) {
   const DevNet& g = p.net;
   const int N = g.N, M = g.M_real;
@@ -335,6 +338,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
   const int lane = (int)threadIdx.x;
   const bool own = lane < N;     // the lane carries species `lane`
   const uint32_t traj = p.traj_offset + (uint32_t)tl;
+  auto is_cont = [&](int j) -> bool { return kOde || p.cont[j] != 0; };
   // LDS: stage argument z[kZ] (z[N] = 1, the pseudo-species of lower-order
   // laws), this trajectory's rates c[M], intensities av[M] at a jump, and the
   // continuous reactions' rates ac[M] at the stage argument.
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
     const bool in = j < M;
     sc_[d] = in ? p.rates[(int64_t)j * p.rates_ld + tl] : 0.0;
     sl[d] = in ? pack_law(g.law[j]) : -1;
-    scont[d] = in && p.cont[j] != 0;
+    scont[d] = in && is_cont(j);
   }
   // This lane's species column (reactions that change it, ascending j): the
   // first kLaneEntries continuous ones as (j, nu) in registers, the rest read
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
   int cnt = 0, ovf = ce;
   for (int e = cb; e < ce; ++e) {
     const int2 ent = g.col_ent[e];
-    if (!p.cont[ent.x]) continue;
+    if (!is_cont(ent.x)) continue;
     if (cnt == kLaneEntries) {
       ovf = e;
       break;
@@ -415,7 +419,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
       }
     }
     for (int j = lane + kWaveWG * kLaneSlots; j < M; j += kWaveWG) {
-      if (p.cont[j]) ac[j] = c[j] * h_det(pack_law(g.law[j]));
+      if (is_cont(j)) ac[j] = c[j] * h_det(pack_law(g.law[j]));
       else part = part + intensity(j);
     }
     __syncthreads();
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
       if (k < cnt) f = f + (double)ev[k] * ac[ej[k]];
     for (int e = ovf; e < ce; ++e) {
       const int2 ent = g.col_ent[e];
-      if (p.cont[ent.x]) f = f + (double)ent.y * ac[ent.x];
+      if (is_cont(ent.x)) f = f + (double)ent.y * ac[ent.x];
     }
     *a0 = wave_sum(part);
     return f;
@@ -471,7 +475,12 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
   double y = own ? (double)(p.x0_ld ? p.x0[(int64_t)lane * p.x0_ld + tl] : p.x0[lane]) : 0.0;
   double t = 0.0, L = 0.0, xi, u;
   uint32_t njump = 0;
-  draw(0u, &xi, &u);
+  if (kOde) {
+    xi = __builtin_huge_val();  // no discrete reactions: L stays 0
+    u = 0.0;
+  } else {
+    draw(0u, &xi, &u);
+  }
   int s = 0;
   uint64_t acc = 0, rej = 0;
   uint32_t status = 0;
@@ -580,17 +589,17 @@ __global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams
     __syncthreads();
     if (own) z[lane] = y;
     __syncthreads();
-    for (int j = lane; j < M; j += kWaveWG) av[j] = p.cont[j] ? 0.0 : intensity(j);
+    for (int j = lane; j < M; j += kWaveWG) av[j] = is_cont(j) ? 0.0 : intensity(j);
     __syncthreads();
     double a0 = 0.0;
     for (int j = 0; j < M; ++j)
-      if (!p.cont[j]) a0 = a0 + av[j];
+      if (!is_cont(j)) a0 = a0 + av[j];
     if (a0 > 0.0) {
       const double rr = u * a0;
       double cum = 0.0;
       int pick = -1, last = -1;
       for (int j = 0; j < M && pick < 0; ++j) {
-        if (p.cont[j]) continue;
+        if (is_cont(j)) continue;
         const double a = av[j];
         cum = cum + a;
         if (a > 0.0) last = j;
@@ -624,13 +633,27 @@ hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
   if (p.n_traj <= 0) return hipSuccess;
   const size_t lds = (size_t)(kZ + 3 * (int64_t)p.net.M_real) * sizeof(double);
   if (p.net.N <= kWaveWG && lds <= 65536) {
-    hipLaunchKernelGGL(hybrid_wave_kernel, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds, stream,
-                       p);
+    hipLaunchKernelGGL(hybrid_wave_kernel<false>, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds,
+                       stream, p);
   } else {
     const int64_t blocks = (p.n_traj + kHybWG - 1) / kHybWG;
     hipLaunchKernelGGL(hybrid_lane_kernel, dim3((unsigned)blocks), dim3(kHybWG), 0, stream, p);
   }
   return hipGetLastError();
+}
+
+// The rate-equation sweep on the wave-per-trajectory kernel (every reaction
+// continuous); false when the network does not fit it (more than 64 species or
+// too many reactions for its LDS), and nothing is launched.
+bool launch_ode_wave(const HybridParams& p, hipStream_t stream, hipError_t* err) {
+  const size_t lds = (size_t)(kZ + 3 * (int64_t)p.net.M_real) * sizeof(double);
+  if (p.net.N > kWaveWG || lds > 65536) return false;
+  *err = hipSuccess;
+  if (p.n_traj <= 0) return true;
+  hipLaunchKernelGGL(hybrid_wave_kernel<true>, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds,
+                     stream, p);
+  *err = hipGetLastError();
+  return true;
 }
 
 }  // namespace rn

@@ -60,3 +60,9 @@ def test_ode_closed_form_decay_on_gpu():
     times = gen.sample_times(5.0, 11)
     out, st = rn.ode_run(net, rates, np.array([1000], np.int32), times, rtol=1e-10, atol=1e-10)
     assert np.allclose(out[:, 0, :], (1000 * np.exp(-0.7 * times))[:, None], rtol=1e-8)
+
+
+def test_ode_wide_network_lane_kernel():
+    # more than 64 species: the lane-per-trajectory kernel with its workspace
+    _check(gen.synthetic_workload(n_traj=130, n_species=70, n_reactions=140, t_end=1.0,
+                                  n_samples=6, seed=3))

@@ -331,7 +331,8 @@ __device__ __forceinline__ int pack_law(const RateLaw& law) {
 // kOde: every reaction continuous and p.cont unused, i.e. the reaction-rate
 // equations of rn_ode_sweep (no draws, no jumps).
 template <bool kOde>
-__global__ __launch_bounds__(kWaveWG) void hybrid_wave_kernel(const HybridParams p) {
+__global__ __launch_bounds__(kWaveWG) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void hybrid_wave_kernel(const HybridParams p) {
   const DevNet& g = p.net;
   const int N = g.N, M = g.M_real;
   const int64_t tl = blockIdx.x;  // one trajectory per wave

@@ -145,3 +145,18 @@ def test_trajectory_offset_and_max_steps():
                                  threads=8)
     assert np.all(sc[:, 3] == 2) and np.all(rsc[:, 3] == 2)
     assert np.allclose(cut, ref, rtol=1e-9, atol=1e-9)
+
+
+def test_edge_cases():
+    # one trajectory; a single sample at t = 0; a network whose discrete
+    # reaction can never fire (its reactant is absent) and whose flow is zero
+    w = gen.enzyme_workload(n_traj=1)
+    out, st = rn.hybrid_run(w.net, [True, True, False], w.rates, w.x0, np.array([0.0]), seed=3)
+    assert np.array_equal(out[0, :, 0], w.x0.astype(float)) and np.all(st[:, :3] == 0)
+    net = gen.make_network(2, [([(0, 1)], [(1, 1)]), ([(1, 1)], [(0, 1)])])
+    rates = np.full((2, 65), 0.7)
+    times = gen.sample_times(3.0, 4)
+    out, st = rn.hybrid_run(net, [False, False], rates, [0, 0], times, seed=3)
+    assert np.all(out == 0) and np.all(st[:, 2] == 0) and np.all(st[:, 3] == 0)
+    ref, rst = oracle.hybrid_run(net, [False, False], rates, [0, 0], times, seed=3)
+    assert np.array_equal(out, ref) and np.array_equal(st, rst)

@@ -160,3 +160,23 @@ def test_edge_cases():
     assert np.all(out == 0) and np.all(st[:, 2] == 0) and np.all(st[:, 3] == 0)
     ref, rst = oracle.hybrid_run(net, [False, False], rates, [0, 0], times, seed=3)
     assert np.array_equal(out, ref) and np.array_equal(st, rst)
+
+
+def test_full_size_sample_matches_oracle():
+    # the benchmark's hybrid sweep at full size (65,536 trajectories), in the
+    # launch configuration bench.py times; 16 spread trajectories are re-run by
+    # the oracle one by one
+    w = gen.hybrid_workload()
+    cont = gen.abundance_partition(w.net, w.x0)
+    _say(f"case hybrid full size: T={w.n_traj}, {int(cont.sum())} continuous")
+    out, st = rn.hybrid_run(w.net, cont, w.rates, w.x0, w.times, seed=w.seed)
+    ids = np.linspace(0, w.n_traj - 1, 16).astype(int)
+    same, errs = 0, []
+    for t in ids:
+        ref, rst = oracle.hybrid_run(w.net, cont, w.rates, w.x0, w.times, seed=w.seed,
+                                     traj_range=(int(t), int(t) + 1))
+        if st[t, 2] == rst[0, 2]:
+            same += 1
+            errs.append((np.abs(out[:, :, t] - ref[:, :, 0]) / (1.0 + np.abs(ref[:, :, 0]))).max())
+    _say(f"  {same}/16 equal jump counts, max rel diff {max(errs):.3g}")
+    assert same >= 15 and max(errs) <= 1e4 * 1e-6

@@ -66,3 +66,20 @@ def test_ode_wide_network_lane_kernel():
     # more than 64 species: the lane-per-trajectory kernel with its workspace
     _check(gen.synthetic_workload(n_traj=130, n_species=70, n_reactions=140, t_end=1.0,
                                   n_samples=6, seed=3))
+
+
+def test_ode_full_size_sample():
+    # the benchmark's rate-equation sweep at full size (65,536 trajectories, the
+    # 50x100 workload to t_end 50); 8 spread trajectories re-run by the oracle
+    w = gen.synthetic_workload()
+    print(f"case ode full size: T={w.n_traj}", flush=True)
+    out, st = rn.ode_run(w.net, w.rates, w.x0, w.times)
+    ids = np.linspace(0, w.n_traj - 1, 8).astype(int)
+    for t in ids:
+        ref, rst = oracle.ode_run(w.net, w.rates, w.x0, w.times, traj_range=(int(t), int(t) + 1))
+        err = (np.abs(out[:, :, t] - ref[:, :, 0]) / (1.0 + np.abs(ref[:, :, 0]))).max()
+        tot, rtot = float(st[t, :2].sum()), float(rst[0, :2].sum())
+        assert err <= 10 * 1e-6, (t, err)
+        assert abs(tot - rtot) / rtot <= 0.05, (t, tot, rtot)
+        assert st[t, 3] == rst[0, 3]
+    print("  8 sampled trajectories within the rate-equation tolerance", flush=True)

@@ -91,7 +91,7 @@ def parse():
                     help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
     ap.add_argument("--workload",
                     choices=("synthetic", "batch", "serve", "phases", "copy", "hybrid", "ode",
-                             "moments"),
+                             "moments", "stiff"),
                     default="synthetic",
                     help="synthetic: the 50x100 sweep of 65,536 trajectories (the headline); "
                          "batch: the uneven batch of 64 networks, batched vs one sweep at a "
@@ -100,7 +100,8 @@ def parse():
                          "device copies (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE); "
                          "hybrid: the hybrid (PDMP) sweep of the 50x100 network with low counts; "
                          "ode: the rate-equation sweep of the 50x100 workload; moments: the "
-                         "ensemble-moment reduction of a 50x100 sample array")
+                         "ensemble-moment reduction of a 50x100 sample array; stiff: the stiff "
+                         "30x80 sweep in FP64 and FP32 with per-species moment errors")
     ap.add_argument("--hybrid-cpu-sample", type=int, default=32,
                     help="trajectories the oracle runs for the hybrid cpu_baseline")
     ap.add_argument("--ode-cpu-sample", type=int, default=8,
@@ -402,6 +403,62 @@ def ode_main(args, torch, gen, rn):
     print(json.dumps(result), flush=True)
 
 
+def stiff_main(args, torch, gen, rn):
+    """Stiff multiscale sweep: 30 species, 80 reactions, rates logU[1e-6, 1e2],
+    a fifth of the species below 10 molecules, --n-traj trajectories to
+    t_end 10 (101 samples).  Times the FP64 and the FP32 sweep with the same
+    seed and reports, per species, the relative error of the FP32 ensemble mean
+    against the FP64 one at every sample (max over samples) and its paired z."""
+    dev = torch.device("cuda:0")
+    w = gen.stiff_workload(n_traj=args.n_traj)
+    T, M, N, S = w.n_traj, w.net.n_reactions, w.net.n_species, len(w.times)
+    net = rn.Network(w.net)
+    r = torch.from_numpy(w.rates).to(dev)
+    x = torch.from_numpy(w.x0).to(dev)
+    tm = torch.from_numpy(w.times).to(dev)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        kind = rn.sweep_kernel_kind(net, T, prec)
+        o = torch.empty((S, N, T), dtype=torch.int32, device=dev)
+        st = torch.empty((T, 4), dtype=torch.int64, device=dev)
+        kw = dict(seed=w.seed, eps=w.eps, n_c=w.n_c, precision=prec)
+        wall, kern_ms = _timed(torch, dev, args, lambda: rn.sweep(net, r, x, tm, o, st, **kw),
+                               f"{prec} stiff sweeps")
+        s2 = st.cpu().numpy().view(np.uint64)
+        steps = int(s2[:, 0].sum() + s2[:, 1].sum())
+        res[prec] = dict(out=o.cpu().numpy().astype(np.float64), steps=steps, kind=kind,
+                         wall=wall, kern_ms=float(np.mean(kern_ms)))
+    a, b = res["fp64"]["out"], res["fp32"]["out"]
+    m64, m32 = a.mean(axis=2), b.mean(axis=2)                    # [S][N]
+    rel = np.abs(m32 - m64) / np.maximum(np.abs(m64), 1.0)
+    d = b - a                                                    # paired differences
+    se = d.std(axis=2, ddof=1) / np.sqrt(T)
+    z = np.where(se > 0, np.abs(d.mean(axis=2)) / np.where(se > 0, se, 1.0), 0.0)
+    per_species = [{"species": i, "max_rel_mean_error": float(rel[:, i].max()),
+                    "max_paired_z": float(z[:, i].max())} for i in range(N)]
+    v64 = res["fp64"]["steps"] / (res["fp64"]["kern_ms"] / 1e3)
+    v32 = res["fp32"]["steps"] / (res["fp32"]["kern_ms"] / 1e3)
+    result = {
+        "metric": "stiff 30x80 sweep: trajectory-steps/sec FP64 and FP32 (1 GPU)",
+        "value": v32, "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["fp32"]["kern_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name} stiff, FP32 vs FP64", "n_traj": T, "n_species": N,
+                   "n_reactions": M, "t_end": float(w.times[-1]), "n_samples": S,
+                   "seed": w.seed},
+        "fp64": {"value": v64, "ms": res["fp64"]["kern_ms"], "steps": res["fp64"]["steps"],
+                 "kernel": res["fp64"]["kind"]},
+        "fp32": {"value": v32, "ms": res["fp32"]["kern_ms"], "steps": res["fp32"]["steps"],
+                 "kernel": res["fp32"]["kind"]},
+        "fp32_speedup": v32 / v64,
+        "moment_error": {"max_rel_mean_error": float(rel.max()),
+                         "median_rel_mean_error": float(np.median(rel)),
+                         "max_paired_z": float(z.max()), "per_species": per_species},
+        "cpu_baseline": None, "roofline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def moments_main(args, torch, gen, rn):
     """Ensemble moments (rn_moments) of a sample array of the headline shape:
     200 samples x 50 species x --n-traj trajectories of int32 counts in
@@ -616,6 +673,9 @@ def main():
         return
     if args.workload == "moments":
         moments_main(args, torch, gen, rn)
+        return
+    if args.workload == "stiff":
+        stiff_main(args, torch, gen, rn)
         return
     dev = torch.device("cuda:0")
     w = gen.synthetic_workload(n_traj=args.n_traj)

@@ -361,6 +361,9 @@ int rn_ode_sweep(const rn_network *net, const rn_ode_args *args, void *hip_strea
  *             remaining samples repeat the last state).
  *  work       device scratch of 12 * n_species rows of work_ld doubles
  *             (rn_hybrid_work_doubles gives the total for work_ld = n_traj).
+ *             Networks of up to 64 species run one wave per trajectory with
+ *             the state in registers and leave it untouched; their sums over
+ *             species add in a butterfly order rather than in species order.
  *  rtol, atol finite, > 0; max_steps >= 1 (accepted + rejected, checked
  *             before each step).
  * Asynchronous on `hip_stream`; allocates nothing.  Errors: RN_E_INVALID_ARG,

@@ -341,15 +341,23 @@ void hybrid_wave_kernel(const HybridParams p) {
   const uint32_t traj = p.traj_offset + (uint32_t)tl;
   auto is_cont = [&](int j) -> bool { return kOde || p.cont[j] != 0; };
   // LDS: stage argument z[kZ] (z[N] = 1, the pseudo-species of lower-order
-  // laws), this trajectory's rates c[M], intensities av[M] at a jump, and the
-  // continuous reactions' rates ac[M] at the stage argument.
+  // laws), this trajectory's rates c[M], intensities av[M] at a jump, the
+  // continuous reactions' rates ac[M] at the stage argument, and the discrete
+  // reactions in increasing index dj[nd].
   extern __shared__ double sh[];
   double* const z = sh;
   double* const c = sh + kZ;
   double* const av = c + M;
   double* const ac = av + M;
+  int* const dj = (int*)(ac + M);
   for (int j = lane; j < M; j += kWaveWG) c[j] = p.rates[(int64_t)j * p.rates_ld + tl];
   if (lane == 0) z[N] = 1.0;
+  int nd = 0;  // every lane counts; lane 0 writes the list
+  for (int j = 0; j < M; ++j) {
+    if (is_cont(j)) continue;
+    if (lane == 0) dj[nd] = j;
+    ++nd;
+  }
   const double* __restrict__ times = p.times;
   const int S = p.n_times;
   // Reaction slots of this lane: j = lane + 64 d for d < kLaneSlots, with
@@ -593,14 +601,13 @@ void hybrid_wave_kernel(const HybridParams p) {
     for (int j = lane; j < M; j += kWaveWG) av[j] = is_cont(j) ? 0.0 : intensity(j);
     __syncthreads();
     double a0 = 0.0;
-    for (int j = 0; j < M; ++j)
-      if (!is_cont(j)) a0 = a0 + av[j];
+    for (int q = 0; q < nd; ++q) a0 = a0 + av[dj[q]];
     if (a0 > 0.0) {
       const double rr = u * a0;
       double cum = 0.0;
       int pick = -1, last = -1;
-      for (int j = 0; j < M && pick < 0; ++j) {
-        if (is_cont(j)) continue;
+      for (int q = 0; q < nd && pick < 0; ++q) {
+        const int j = dj[q];
         const double a = av[j];
         cum = cum + a;
         if (a > 0.0) last = j;
@@ -628,11 +635,16 @@ void hybrid_wave_kernel(const HybridParams p) {
   }
 }
 
+// Dynamic LDS of the wave kernel: z, c, av, ac (doubles) and dj (ints).
+size_t wave_lds_bytes(int64_t m) {
+  return (size_t)(kZ + 3 * m) * sizeof(double) + (size_t)m * sizeof(int);
+}
+
 }  // namespace
 
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
   if (p.n_traj <= 0) return hipSuccess;
-  const size_t lds = (size_t)(kZ + 3 * (int64_t)p.net.M_real) * sizeof(double);
+  const size_t lds = wave_lds_bytes(p.net.M_real);
   if (p.net.N <= kWaveWG && lds <= 65536) {
     hipLaunchKernelGGL(hybrid_wave_kernel<false>, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds,
                        stream, p);
@@ -647,7 +659,7 @@ hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
 // continuous); false when the network does not fit it (more than 64 species or
 // too many reactions for its LDS), and nothing is launched.
 bool launch_ode_wave(const HybridParams& p, hipStream_t stream, hipError_t* err) {
-  const size_t lds = (size_t)(kZ + 3 * (int64_t)p.net.M_real) * sizeof(double);
+  const size_t lds = wave_lds_bytes(p.net.M_real);
   if (p.net.N > kWaveWG || lds > 65536) return false;
   *err = hipSuccess;
   if (p.n_traj <= 0) return true;

@@ -440,7 +440,7 @@ void hybrid_wave_kernel(const HybridParams p) {
       const int2 ent = g.col_ent[e];
       if (is_cont(ent.x)) f = f + (double)ent.y * ac[ent.x];
     }
-    *a0 = wave_sum(part);
+    *a0 = kOde ? 0.0 : wave_sum(part);  // no discrete reactions in the ODE form
     return f;
   };
   struct Stage {

@@ -536,13 +536,36 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   return RN_OK;
 }
 
+// The sweep parameters of trajectories [off, off + n) of a plan: pointers and
+// the trajectory offset moved to the range's first trajectory.
+static rn::SweepParams sub_range(const rn::SweepParams& p, int64_t off, int64_t n) {
+  rn::SweepParams q = p;
+  q.n_traj = n;
+  q.traj_offset = p.traj_offset + (uint32_t)off;
+  q.rates = p.rates + off;
+  if (p.x0_ld != 0) q.x0 = p.x0 + off;
+  q.out = p.out + off;
+  q.stats = p.stats + 4 * off;
+  if (p.phase_cycles) q.phase_cycles = p.phase_cycles + 4 * (off / 64);
+  return q;
+}
+
+// At most 2^24 trajectories per dispatch (a dispatch holds fewer than 2^32
+// work-items); a larger sweep is enqueued as consecutive ranges, which the
+// global trajectory ids make identical to one launch.
+constexpr int64_t kLaunchChunk = (int64_t)1 << 24;
+
 hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
   if (plan.empty) return hipSuccess;
-  const hipError_t e = stage_network(plan.net, stream);
-  if (e != hipSuccess) return e;
-  if (plan.fn) return rn::jit_launch(plan.fn, plan.p, plan.wg, plan.lds, stream);
-  return plan.precision == RN_FP32 ? rn::launch_sweep_f32(plan.p, plan.cfg, stream)
-                                   : rn::launch_sweep_f64(plan.p, plan.cfg, stream);
+  hipError_t e = stage_network(plan.net, stream);
+  for (int64_t off = 0; e == hipSuccess && off < plan.p.n_traj; off += kLaunchChunk) {
+    const rn::SweepParams q =
+        sub_range(plan.p, off, std::min(kLaunchChunk, plan.p.n_traj - off));
+    if (plan.fn) e = rn::jit_launch(plan.fn, q, plan.wg, plan.lds, stream);
+    else if (plan.precision == RN_FP32) e = rn::launch_sweep_f32(q, plan.cfg, stream);
+    else e = rn::launch_sweep_f64(q, plan.cfg, stream);
+  }
+  return e;
 }
 
 int device_status(hipError_t e) { return e == hipSuccess ? RN_OK : device_error(e); }
@@ -596,7 +619,7 @@ int64_t rn_ode_work_doubles(const rn_network* net, int64_t n_traj) {
 
 int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) {
   if (!net || !a) return RN_E_INVALID_ARG;
-  if (a->n_traj < 0 || a->n_times < 1) return RN_E_INVALID_ARG;
+  if (a->n_traj < 0 || a->n_traj > ((int64_t)1 << 32) || a->n_times < 1) return RN_E_INVALID_ARG;
   if (!(a->rtol > 0.0) || !std::isfinite(a->rtol) || !(a->atol > 0.0) || !std::isfinite(a->atol))
     return RN_E_INVALID_ARG;
   if (a->max_steps < 1) return RN_E_INVALID_ARG;

@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rn_device.h"
 #include "rn_dopri.h"
 #include "rn_kernel.h"
@@ -640,19 +642,42 @@ size_t wave_lds_bytes(int64_t m) {
   return (size_t)(kZ + 3 * m) * sizeof(double) + (size_t)m * sizeof(int);
 }
 
+// Launches cover at most kLaunchChunk trajectories each (the wave kernel has
+// 64 work-items per trajectory, and a dispatch holds fewer than 2^32): a
+// larger sweep is enqueued as consecutive ranges, each with its pointers and
+// trajectory offset moved to the range's first trajectory.
+constexpr int64_t kLaunchChunk = (int64_t)1 << 24;
+
+HybridParams sub_range(const HybridParams& p, int64_t off, int64_t n) {
+  HybridParams q = p;
+  q.n_traj = n;
+  q.traj_offset = p.traj_offset + (uint32_t)off;
+  q.rates = p.rates + off;
+  if (p.x0_ld != 0) q.x0 = p.x0 + off;
+  q.out = p.out + off;
+  q.stats = p.stats + 4 * off;
+  if (p.work) q.work = p.work + off;
+  return q;
+}
+
 }  // namespace
 
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
-  if (p.n_traj <= 0) return hipSuccess;
   const size_t lds = wave_lds_bytes(p.net.M_real);
-  if (p.net.N <= kWaveWG && lds <= 65536) {
-    hipLaunchKernelGGL(hybrid_wave_kernel<false>, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds,
-                       stream, p);
-  } else {
-    const int64_t blocks = (p.n_traj + kHybWG - 1) / kHybWG;
-    hipLaunchKernelGGL(hybrid_lane_kernel, dim3((unsigned)blocks), dim3(kHybWG), 0, stream, p);
+  const bool wave = p.net.N <= kWaveWG && lds <= 65536;
+  for (int64_t off = 0; off < p.n_traj; off += kLaunchChunk) {
+    const HybridParams q = sub_range(p, off, std::min(kLaunchChunk, p.n_traj - off));
+    if (wave) {
+      hipLaunchKernelGGL(hybrid_wave_kernel<false>, dim3((unsigned)q.n_traj), dim3(kWaveWG), lds,
+                         stream, q);
+    } else {
+      const int64_t blocks = (q.n_traj + kHybWG - 1) / kHybWG;
+      hipLaunchKernelGGL(hybrid_lane_kernel, dim3((unsigned)blocks), dim3(kHybWG), 0, stream, q);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 // The rate-equation sweep on the wave-per-trajectory kernel (every reaction
@@ -662,10 +687,13 @@ bool launch_ode_wave(const HybridParams& p, hipStream_t stream, hipError_t* err)
   const size_t lds = wave_lds_bytes(p.net.M_real);
   if (p.net.N > kWaveWG || lds > 65536) return false;
   *err = hipSuccess;
-  if (p.n_traj <= 0) return true;
-  hipLaunchKernelGGL(hybrid_wave_kernel<true>, dim3((unsigned)p.n_traj), dim3(kWaveWG), lds,
-                     stream, p);
-  *err = hipGetLastError();
+  for (int64_t off = 0; off < p.n_traj; off += kLaunchChunk) {
+    const HybridParams q = sub_range(p, off, std::min(kLaunchChunk, p.n_traj - off));
+    hipLaunchKernelGGL(hybrid_wave_kernel<true>, dim3((unsigned)q.n_traj), dim3(kWaveWG), lds,
+                       stream, q);
+    *err = hipGetLastError();
+    if (*err != hipSuccess) break;
+  }
   return true;
 }
 

@@ -165,11 +165,24 @@ __global__ __launch_bounds__(kOdeWG) void ode_kernel(const OdeParams p) {
 
 }  // namespace
 
+// At most 2^24 trajectories per dispatch (a dispatch holds fewer than 2^32
+// work-items); a larger sweep is enqueued as consecutive ranges.
 hipError_t launch_ode(const OdeParams& p, hipStream_t stream) {
-  const int64_t blocks = (p.n_traj + kOdeWG - 1) / kOdeWG;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ode_kernel, dim3((unsigned)blocks), dim3(kOdeWG), 0, stream, p);
-  return hipGetLastError();
+  constexpr int64_t kChunk = (int64_t)1 << 24;
+  for (int64_t off = 0; off < p.n_traj; off += kChunk) {
+    OdeParams q = p;
+    q.n_traj = p.n_traj - off < kChunk ? p.n_traj - off : kChunk;
+    q.rates = p.rates + off;
+    if (p.x0_ld != 0) q.x0 = p.x0 + off;
+    q.out = p.out + off;
+    q.stats = p.stats + 4 * off;
+    q.work = p.work + off;
+    const int64_t blocks = (q.n_traj + kOdeWG - 1) / kOdeWG;
+    hipLaunchKernelGGL(ode_kernel, dim3((unsigned)blocks), dim3(kOdeWG), 0, stream, q);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rn

@@ -76,7 +76,17 @@ def test_fp32_stiff_distribution():
     _fp32_vs_oracle(gen.stiff_workload(n_traj=2048), 105, 206)
 
 
+_PAIRED = {}
+
+
 def _paired(w, seed):
+    key = (w.name, w.n_traj, seed)
+    if key not in _PAIRED:
+        _PAIRED[key] = _paired_run(w, seed)
+    return _PAIRED[key]
+
+
+def _paired_run(w, seed):
     o64, s64 = rn.run(w.net, w.rates, w.x0, w.times, seed=seed)
     o32, s32 = rn.run(w.net, w.rates, w.x0, w.times, seed=seed, precision="fp32")
     d = o32.astype(float) - o64.astype(float)
@@ -95,16 +105,50 @@ def _paired(w, seed):
     return rel, zp, same
 
 
+# The stated FP32 error bound: relative mean error at most 1e-3 in every cell.
+REL_BOUND = 1e-3
+
+
 def test_fp32_paired_enzyme():
     rel, zp, same = _paired(gen.enzyme_workload(), 7)
     assert np.mean(zp > 3) <= 0.01 and zp.max() <= 5.0
-    assert np.median(rel) <= 1e-3
+    assert rel.max() <= REL_BOUND, f"max paired relative mean error {rel.max():.3g}"
 
 
 def test_fp32_paired_stiff_subset():
+    # no systematic bias: the paired differences are Monte Carlo noise
     rel, zp, same = _paired(gen.stiff_workload(n_traj=8192), 8)
     assert np.mean(zp > 3) <= 0.01 and zp.max() <= 5.0
-    assert np.median(rel) <= 1e-3
+    assert np.median(rel) <= REL_BOUND
+
+
+@pytest.mark.xfail(strict=False,
+                   reason="bound not met: measured max paired relative mean error 3.8e-3 at "
+                          "8,192 trajectories (1.6e-3 at 65,536); trajectories that a float "
+                          "rounding has decorrelated from their FP64 twins leave paired noise "
+                          "of that size in low-count cells (largest paired z 2.9)")
+def test_fp32_paired_stiff_max_error_bound():
+    rel, zp, same = _paired(gen.stiff_workload(n_traj=8192), 8)
+    assert rel.max() <= REL_BOUND, f"max paired relative mean error {rel.max():.3g}"
+
+
+def test_fp32_stiff_full_launch_vs_oracle():
+    # The stiff configuration at its stated size: 65,536 trajectories in one
+    # FP32 launch (256-lane workgroups, one wave per SIMD), of which a
+    # contiguous block of 8,192 is compared with the FP64 oracle on the same
+    # rate constants (independent seeds), by the per-cell rule above.
+    w = gen.stiff_workload()
+    assert w.n_traj == 65536
+    assert rn.sweep_kernel_kind(rn.Network(w.net), w.n_traj, "fp32") in (0, 1)
+    _say(f"case fp32 stiff full launch: T={w.n_traj}")
+    out, st = rn.run(w.net, w.rates, w.x0, w.times, seed=109, precision="fp32")
+    assert out.min() >= 0
+    assert np.all((st[:, 3] & rn.ST_MAXSTEPS) == 0)
+    a, b = 24576, 24576 + 8192
+    ref, rst, _ = oracle.run(w.net, w.rates, w.x0, w.times, seed=210, traj_range=(a, b),
+                             threads=16)
+    assert np.all((rst[:, 3] & 2) == 0)
+    _agree(out[:, :, a:b], ref, "fp32 stiff block [24576, 32768) of the full launch vs fp64 oracle")
 
 
 def test_fp32_decay_eighty_leaps_and_fp64_agreement():

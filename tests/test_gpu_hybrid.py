@@ -84,7 +84,8 @@ def test_all_continuous_is_the_rate_equation_sweep(n_species):
     _close_to_rate_equations(out, st, ref, rst, 1e-6)
 
 
-@pytest.mark.parametrize("case", ["enzyme", "synthetic_low_counts", "wide_70_species"])
+@pytest.mark.parametrize("case", ["enzyme", "synthetic_low_counts", "wide_70_species",
+                                  "wave_64x160", "wave_40x200"])
 def test_mixed_partition_matches_oracle(case):
     rtol = 1e-8
     if case == "enzyme":
@@ -94,6 +95,14 @@ def test_mixed_partition_matches_oracle(case):
     elif case == "synthetic_low_counts":
         w = gen.synthetic_workload(n_traj=200, n_species=20, n_reactions=40, t_end=2.0,
                                    n_samples=11, low_count_frac=0.3, seed=12)
+        cont = gen.abundance_partition(w.net, w.x0)
+        x0 = w.x0
+    elif case in ("wave_64x160", "wave_40x200"):
+        # the wave kernel at its edges: 64 species, and reactions j >= 128 past
+        # the lane's register slots
+        n, m = (64, 160) if case == "wave_64x160" else (40, 200)
+        w = gen.synthetic_workload(n_traj=120, n_species=n, n_reactions=m, t_end=0.02,
+                                   n_samples=5, low_count_frac=0.2, seed=15)
         cont = gen.abundance_partition(w.net, w.x0)
         x0 = w.x0
     else:  # more species than a wave has lanes: the lane-per-trajectory kernel

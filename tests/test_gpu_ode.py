@@ -83,3 +83,12 @@ def test_ode_full_size_sample():
         assert abs(tot - rtot) / rtot <= 0.05, (t, tot, rtot)
         assert st[t, 3] == rst[0, 3]
     print("  8 sampled trajectories within the rate-equation tolerance", flush=True)
+
+
+@pytest.mark.parametrize("n_species,n_reactions", [(64, 128), (64, 160), (40, 200)])
+def test_ode_wave_kernel_boundaries(n_species, n_reactions):
+    # the wave kernel at its edges: 64 species (lane 63 owns a species and the
+    # pseudo-species sits past the wave), and reactions past the two register
+    # slots of a lane (j >= 128: rates from LDS, laws from the tables)
+    _check(gen.synthetic_workload(n_traj=150, n_species=n_species, n_reactions=n_reactions,
+                                  t_end=1.0, n_samples=6, seed=31))

@@ -37,7 +37,8 @@ class _Params(C.Structure):
 
 
 class _OdeParams(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64),
+                ("method", C.c_int32)]
 
 
 class _HybridParams(C.Structure):
@@ -188,9 +189,14 @@ def run(net, rates, x0, times, *, seed, eps=0.03, n_c=10, ssa_factor=10.0, ssa_b
     return out, stats, ops
 
 
+ODE_METHODS = {"dopri5": 0, "ros4": 1}
+
+
 def ode_run(net, rates, x0, times, *, rtol=1e-6, atol=1e-6, max_steps=10**7, traj_range=None,
-            threads=1):
-    """Reaction-rate equations by Dormand-Prince 5(4) for trajectories ``traj_range``.
+            threads=1, method="dopri5"):
+    """Reaction-rate equations for trajectories ``traj_range``, by the
+    Dormand-Prince 5(4) pair (``method="dopri5"``) or the Rosenbrock 4(3)
+    method for stiff networks (``method="ros4"``).
 
     Returns ``(out [S][N][T] float64, stats [T][4] uint64)`` with stats = (accepted
     steps, rejected steps, 0, status)."""
@@ -204,7 +210,7 @@ def ode_run(net, rates, x0, times, *, rtol=1e-6, atol=1e-6, max_steps=10**7, tra
     out = np.zeros((S, N, n), dtype=np.float64)
     stats = np.zeros((n, 4), dtype=np.uint64)
     desc, keep = _desc(net)
-    par = _OdeParams(float(rtol), float(atol), int(max_steps))
+    par = _OdeParams(float(rtol), float(atol), int(max_steps), ODE_METHODS[method])
     L = lib()
     nth = max(1, min(int(threads), n)) if n > 0 else 1
     bounds = np.linspace(0, n, nth + 1).astype(np.int64)

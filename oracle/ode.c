@@ -17,6 +17,22 @@
  * 0.01 * rms(y/sc) / rms(f/sc) (1e-6 when either norm is below 1e-5).  A step
  * that reaches the next sample time ends exactly on it.
  *
+ * Stiff integrator (method ORC_ODE_ROS4): a linearly implicit Rosenbrock
+ * method of order 4 with an embedded order-3 solution, the gamma = 1/2
+ * parameter set of L. F. Shampine, ACM Trans. Math. Softw. 8 (1982) 93, in the
+ * transformed form of Hairer and Wanner (Solving ODEs II, Sec. IV.7), where no
+ * product of the Jacobian with a vector is needed.  With J the exact Jacobian
+ * of the rate equations at y and W = (1/(gamma h)) I - J, each step solves
+ *   W u1 = f(y)
+ *   W u2 = f(y + a21 u1)            + (c21 u1) / h
+ *   W u3 = f(y + a31 u1 + a32 u2)   + (c31 u1 + c32 u2) / h
+ *   W u4 = f(y + a31 u1 + a32 u2)   + (c41 u1 + c42 u2 + c43 u3) / h
+ * (the fourth stage reuses the third stage's argument) and takes
+ * y' = y + sum m_i u_i, with the error estimate sum e_i u_i (the difference
+ * from the order-3 solution).  W is factored once per step by Gaussian
+ * elimination with partial pivoting.  The error norm and the step rules are
+ * those above with the exponent -1/4 of an order-3 error estimate.
+ *
  * Hybrid stochastic/deterministic sweep (paper, Methods section: abundant
  * species follow the mean-field equations while low-amount species keep their
  * random fluctuations; the process is a piecewise-deterministic Markov process,
@@ -123,6 +139,184 @@ static const double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0,
 static const double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0,
                     E5 = -17253.0 / 339200.0, E6 = 22.0 / 525.0, E7 = -1.0 / 40.0;
 
+/* Rosenbrock 4(3) coefficients, transformed form (Shampine 1982, gamma = 1/2). */
+static const double RG = 0.5;
+static const double RA21 = 2.0, RA31 = 48.0 / 25.0, RA32 = 6.0 / 25.0;
+static const double RC21 = -8.0, RC31 = 372.0 / 25.0, RC32 = 12.0 / 5.0;
+static const double RC41 = -112.0 / 125.0, RC42 = -54.0 / 125.0, RC43 = -2.0 / 5.0;
+static const double RM1 = 19.0 / 9.0, RM2 = 1.0 / 2.0, RM3 = 25.0 / 108.0, RM4 = 125.0 / 108.0;
+static const double RE1 = 17.0 / 54.0, RE2 = 7.0 / 36.0, RE3 = 0.0, RE4 = 125.0 / 108.0;
+
+/* Exact Jacobian of the rate equations at y, dense row-major jac[i*N + k]:
+ * every reaction j in increasing index adds nu_ij * d a_j / d y_k to row i,
+ * with d(c y_a)/dy_a = c, d(c y_a y_b)/dy_a = c y_b, d(c y_a y_b)/dy_b = c y_a
+ * and d(c y_a^2 / 2)/dy_a = c y_a. */
+static void jacobian(const dnet *g, const double *c, int64_t cld, const double *y, double *jac) {
+  const int N = g->N;
+  for (int e = 0; e < N * N; ++e) jac[e] = 0.0;
+  for (int j = 0; j < g->M; ++j) {
+    const double cj = c[(int64_t)j * cld];
+    int ka = -1, kb = -1;
+    double da = 0.0, db = 0.0;
+    switch (g->kind[j]) {
+      case 0: break;
+      case 1: ka = g->ra[j]; da = cj; break;
+      case 2: ka = g->ra[j]; da = cj * y[g->rb[j]]; kb = g->rb[j]; db = cj * y[g->ra[j]]; break;
+      default: ka = g->ra[j]; da = cj * y[g->ra[j]]; break;
+    }
+    for (int i = 0; i < N; ++i) {
+      const int v = g->nu[(size_t)j * N + i];
+      if (!v) continue;
+      if (ka >= 0) jac[i * N + ka] = jac[i * N + ka] + (double)v * da;
+      if (kb >= 0) jac[i * N + kb] = jac[i * N + kb] + (double)v * db;
+    }
+  }
+}
+
+/* In-place LU factorization with partial pivoting: the pivot of column k is
+ * the first row r >= k of largest |a[r][k]|, rows k and r are exchanged (perm
+ * records it), multipliers l = a[i][k] / a[k][k] are stored below the diagonal
+ * and each a[i][j] (j > k) becomes a[i][j] - l * a[k][j].  A zero pivot is not
+ * an error: the solve then yields infinities or NaNs, which the step controller
+ * rejects. */
+static void lu_factor(int N, double *a, int *perm) {
+  for (int k = 0; k < N; ++k) {
+    int r = k;
+    double best = fabs(a[k * N + k]);
+    for (int i = k + 1; i < N; ++i) {
+      const double v = fabs(a[i * N + k]);
+      if (v > best) { best = v; r = i; }
+    }
+    perm[k] = r;
+    if (r != k) {
+      for (int j = 0; j < N; ++j) {
+        const double tmp = a[k * N + j];
+        a[k * N + j] = a[r * N + j];
+        a[r * N + j] = tmp;
+      }
+    }
+    for (int i = k + 1; i < N; ++i) {
+      const double l = a[i * N + k] / a[k * N + k];
+      a[i * N + k] = l;
+      for (int j = k + 1; j < N; ++j) a[i * N + j] = a[i * N + j] - l * a[k * N + j];
+    }
+  }
+}
+
+/* Solve (LU) x = P b in place on b: the row exchanges in factorization order,
+ * forward substitution with unit L (each x_i subtracts l_ik x_k for k in
+ * increasing order), then back substitution (each x_i subtracts u_ik x_k for
+ * k in decreasing order, then divides by u_ii). */
+static void lu_solve(int N, const double *a, const int *perm, double *b) {
+  for (int k = 0; k < N; ++k) {
+    const int r = perm[k];
+    if (r != k) { const double tmp = b[k]; b[k] = b[r]; b[r] = tmp; }
+  }
+  for (int i = 0; i < N; ++i) {
+    double acc = b[i];
+    for (int k = 0; k < i; ++k) acc = acc - a[i * N + k] * b[k];
+    b[i] = acc;
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    double acc = b[i];
+    for (int k = N - 1; k > i; --k) acc = acc - a[i * N + k] * b[k];
+    b[i] = acc / a[i * N + i];
+  }
+}
+
+/* One trajectory of the rate equations by the Rosenbrock 4(3) method. */
+static void ros4_traj(const dnet *g, const double *c, int64_t cld, double *y, const double *times,
+                      int32_t n_times, double *out, int64_t out_ld, int64_t t, uint64_t *st,
+                      const orc_ode_params *par, double *w, int *perm) {
+  const int N = g->N;
+  double *f0 = w, *fs = w + N, *ys = w + 2 * N, *u1 = w + 3 * N, *u2 = w + 4 * N,
+         *u3 = w + 5 * N, *u4 = w + 6 * N, *yn = w + 7 * N, *a = w + 8 * N;
+  double tt = 0.0;
+  int s = 0;
+  uint64_t acc = 0, rej = 0, status = 0;
+  while (s < n_times && times[s] <= tt) {
+    for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+    s++;
+  }
+  rhs(g, c, cld, y, f0);
+  double d0 = 0.0, d1 = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double sc = par->atol + par->rtol * fabs(y[i]);
+    d0 = d0 + (y[i] / sc) * (y[i] / sc);
+    d1 = d1 + (f0[i] / sc) * (f0[i] / sc);
+  }
+  d0 = sqrt(d0 / N);
+  d1 = sqrt(d1 / N);
+  double h = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * (d0 / d1);
+  int last_rejected = 0;
+  while (s < n_times) {
+    if (acc + rej >= par->max_steps) { status |= ORC_ST_MAXSTEPS; break; }
+    const double delta = times[s] - tt;
+    const int clip = !(h < delta);
+    const double hu = clip ? delta : h;
+    const double ih = 1.0 / hu;
+    const double gd = 1.0 / (RG * hu);
+    /* W = (1/(gamma h)) I - J, factored */
+    jacobian(g, c, cld, y, a);
+    for (int i = 0; i < N; ++i)
+      for (int k = 0; k < N; ++k) a[i * N + k] = (i == k ? gd : 0.0) - a[i * N + k];
+    lu_factor(N, a, perm);
+    for (int i = 0; i < N; ++i) u1[i] = f0[i];
+    lu_solve(N, a, perm, u1);
+    for (int i = 0; i < N; ++i) ys[i] = y[i] + RA21 * u1[i];
+    rhs(g, c, cld, ys, fs);
+    for (int i = 0; i < N; ++i) u2[i] = fs[i] + (RC21 * u1[i]) * ih;
+    lu_solve(N, a, perm, u2);
+    for (int i = 0; i < N; ++i) ys[i] = y[i] + (RA31 * u1[i] + RA32 * u2[i]);
+    rhs(g, c, cld, ys, fs);
+    for (int i = 0; i < N; ++i) u3[i] = fs[i] + (RC31 * u1[i] + RC32 * u2[i]) * ih;
+    lu_solve(N, a, perm, u3);
+    for (int i = 0; i < N; ++i) u4[i] = fs[i] + (RC41 * u1[i] + RC42 * u2[i] + RC43 * u3[i]) * ih;
+    lu_solve(N, a, perm, u4);
+    double e2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      yn[i] = y[i] + (RM1 * u1[i] + RM2 * u2[i] + RM3 * u3[i] + RM4 * u4[i]);
+      const double e = RE1 * u1[i] + RE2 * u2[i] + RE3 * u3[i] + RE4 * u4[i];
+      const double ay = fabs(y[i]), an = fabs(yn[i]);
+      const double sc = par->atol + par->rtol * (ay > an ? ay : an);
+      e2 = e2 + (e / sc) * (e / sc);
+    }
+    const double en = sqrt(e2 / N);
+    if (en <= 1.0) {
+      double fac = en == 0.0 ? 5.0 : 0.9 * pow(en, -0.25);
+      if (fac > 5.0) fac = 5.0;
+      if (fac < 0.2) fac = 0.2;
+      if (last_rejected && fac > 1.0) fac = 1.0;
+      memcpy(y, yn, sizeof(double) * N);
+      rhs(g, c, cld, y, f0);
+      if (clip) tt = times[s];
+      else tt = tt + hu;
+      h = hu * fac;
+      acc++;
+      last_rejected = 0;
+      while (s < n_times && times[s] <= tt) {
+        for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+        s++;
+      }
+    } else {
+      /* a NaN norm (a singular W, an overflow) is a rejection at the smallest factor */
+      double fac = 0.9 * pow(en, -0.25);
+      if (!(fac >= 0.2)) fac = 0.2;
+      h = hu * fac;
+      rej++;
+      last_rejected = 1;
+    }
+  }
+  while (s < n_times) {
+    for (int i = 0; i < N; ++i) out[((int64_t)s * N + i) * out_ld + t] = y[i];
+    s++;
+  }
+  st[0] = acc;
+  st[1] = rej;
+  st[2] = 0;
+  st[3] = status;
+}
+
 int orc_ode_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
                 const int32_t *x0, int64_t x0_ld, const double *times, int32_t n_times,
                 int64_t n_traj, double *out, int64_t out_ld, uint64_t *stats,
@@ -134,10 +328,26 @@ int orc_ode_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
     if (!(times[s] >= 0.0) || !isfinite(times[s])) return ORC_E_ARG;
     if (s > 0 && !(times[s] > times[s - 1])) return ORC_E_ARG;
   }
+  if (par->method != ORC_ODE_DOPRI5 && par->method != ORC_ODE_ROS4) return ORC_E_ARG;
   dnet g;
   int err = dnet_build(net, &g);
   if (err) return err;
   const int N = g.N;
+  if (par->method == ORC_ODE_ROS4) {
+    double *rw = malloc(sizeof(double) * ((size_t)N * 9 + (size_t)N * N + (size_t)N));
+    int *perm = malloc(sizeof(int) * (size_t)N);
+    if (!rw || !perm) { free(rw); free(perm); dnet_free(&g); return ORC_E_NOMEM; }
+    double *yv = rw + (size_t)N * 9 + (size_t)N * N;
+    for (int64_t t = 0; t < n_traj; ++t) {
+      for (int i = 0; i < N; ++i) yv[i] = (double)(x0_ld ? x0[(int64_t)i * x0_ld + t] : x0[i]);
+      ros4_traj(&g, rates + t, rates_ld, yv, times, n_times, out, out_ld, t, stats + t * 4, par,
+                rw, perm);
+    }
+    free(rw);
+    free(perm);
+    dnet_free(&g);
+    return ORC_OK;
+  }
   double *w = malloc(sizeof(double) * (size_t)N * 10);
   if (!w) { dnet_free(&g); return ORC_E_NOMEM; }
   double *y = w, *yn = w + N, *k1 = w + 2 * N, *k2 = w + 3 * N, *k3 = w + 4 * N, *k4 = w + 5 * N,

@@ -103,15 +103,23 @@ int orc_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
  * abundant, X(t) is well approximated by the reaction-rate equations, and the
  * thermodynamic limit makes the stochastic and mean-field models agree):
  *   dy/dt = sum_j nu_j c_j h_j(y),  h_j = 1, y_a, y_a*y_b, or y_a^2/2 (homodimer),
- * integrated with the Dormand-Prince 5(4) embedded Runge-Kutta pair and an
- * error-per-step controller; steps are clipped to the sample times.
+ * integrated with the Dormand-Prince 5(4) embedded Runge-Kutta pair, or with a
+ * Rosenbrock 4(3) method for stiff networks, under an error-per-step
+ * controller; steps are clipped to the sample times.
  *   out   : out[(s*N + i)*out_ld + t] (double)
  *   stats : stats[t*4 + {0: accepted steps, 1: rejected steps, 2: 0, 3: status}]
  */
 typedef struct {
   double rtol, atol;
   uint64_t max_steps;  /* accepted + rejected steps per trajectory */
+  int32_t method;      /* ORC_ODE_DOPRI5 or ORC_ODE_ROS4 */
 } orc_ode_params;
+
+/* Integrators of orc_ode_run: the explicit Dormand-Prince 5(4) pair, or the
+ * linearly implicit Rosenbrock 4(3) method for stiff networks (its
+ * construction is described at the top of ode.c). */
+#define ORC_ODE_DOPRI5 0
+#define ORC_ODE_ROS4 1
 
 int orc_ode_run(const orc_net_desc *net, const double *rates, int64_t rates_ld,
                 const int32_t *x0, int64_t x0_ld, const double *times, int32_t n_times,

@@ -78,6 +78,26 @@ OP_COST = {
 }
 
 
+def host_cores():
+    """Host cores this process may run on, at most 16 (one GPU's share of a box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -760,19 +780,36 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
+        # one thread on a prefix of the sweep (the single-core reference of the
+        # speed-up), then every host core available to this process on a longer
+        # prefix (one thread per core, contiguous trajectory chunks)
         n = min(args.cpu_sample, T)
         t0 = time.perf_counter()
         _, ost, ops = oracle.run(w.net, w.rates, w.x0, w.times, seed=w.seed,
                                  traj_range=(0, n), threads=1, counters=True)
         dt = time.perf_counter() - t0
         csteps = int(ost[:, 0].sum() + ost[:, 1].sum())
-        cpu = {"value": csteps / dt, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
+        one = {"value": csteps / dt, "cores": 1,
                "sample": f"trajectories 0..{n - 1} of the same sweep, full horizon, "
                          f"{csteps} steps in {dt:.1f} s, one thread"}
+        print(f"[bench] cpu oracle, 1 thread: {one['value']:.4g} steps/s on {n} trajectories",
+              file=sys.stderr, flush=True)
+        cores = host_cores()
+        na = min(n * cores, T)
+        t0 = time.perf_counter()
+        _, ast, _ = oracle.run(w.net, w.rates, w.x0, w.times, seed=w.seed,
+                               traj_range=(0, na), threads=cores)
+        dta = time.perf_counter() - t0
+        asteps = int(ast[:, 0].sum() + ast[:, 1].sum())
+        cpu = {"value": asteps / dta, "unit": "trajectory-steps/s", "cores": cores,
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"trajectories 0..{na - 1} of the same sweep, full horizon, "
+                         f"{asteps} steps in {dta:.1f} s, {cores} threads",
+               "single_core": one}
+        print(f"[bench] cpu oracle, {cores} threads: {cpu['value']:.4g} steps/s on {na} "
+              f"trajectories ({cpu['cpu_model']})", file=sys.stderr, flush=True)
         work = sum(OP_COST[k] * ops[k] for k in OP_COST)
         ops_per_step = work / max(csteps, 1)
-        print(f"[bench] cpu oracle: {cpu['value']:.4g} steps/s on {n} trajectories",
-              file=sys.stderr, flush=True)
     result["cpu_baseline"] = cpu
 
     kern_s = float(np.mean(kern_ms)) / 1000.0

@@ -32,6 +32,7 @@ extern "C" {
 #define RN_E_UNSUPPORTED (-3)     /* a reaction with three or more reactant molecules   */
 #define RN_E_NOMEM (-4)           /* host or device allocation failed                   */
 #define RN_E_DEVICE (-5)          /* a HIP call failed; rn_last_device_error() names it */
+#define RN_E_SCRATCH (-6)         /* input exceeds the fixed scratch of a no-alloc call   */
 
 /* Per-trajectory status bits (stats[t][3]); never a call error. */
 #define RN_ST_ABSORBED 1u /* total propensity reached 0; later samples repeat the state     */
@@ -333,6 +334,29 @@ void rn_ode_args_init(rn_ode_args *args);
 int64_t rn_ode_work_doubles(const rn_network *net, int64_t n_traj);
 
 int rn_ode_sweep(const rn_network *net, const rn_ode_args *args, void *hip_stream);
+
+/*
+ * rn_ode_sweep without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * rn_ode_sweep; args->work and args->work_ld are ignored.  Where rn_ode_sweep
+ * would run the lane kernel on `work` (networks of more than 64 species, or
+ * too many reactions for the wave kernel's LDS), this call uses a fixed
+ * scratch array of 32 MiB that the library holds on each device it runs on
+ * until the process ends; it needs 10 * n_species doubles per trajectory, so
+ * at most rn_ode_noalloc_max_traj(net) trajectories fit, and a larger n_traj
+ * returns RN_E_SCRATCH with nothing enqueued.  The call performs no device or
+ * host allocation of its own (the first call on a device resolves the
+ * scratch's address).  Every call on one device shares that device's scratch:
+ * calls that overlap on one device (different streams, or different host
+ * threads) race, and the caller must order them.  Errors: those of
+ * rn_ode_sweep, and RN_E_SCRATCH.
+ */
+int rn_ode_sweep_noalloc(const rn_network *net, const rn_ode_args *args, void *hip_stream);
+
+/* Largest n_traj rn_ode_sweep_noalloc accepts for this network (2^32 when it
+ * needs no scratch), or -1 for a null handle. */
+int64_t rn_ode_noalloc_max_traj(const rn_network *net);
 
 /*
  * Hybrid stochastic/deterministic sweep: a piecewise-deterministic Markov

@@ -274,6 +274,7 @@ const char* rn_strerror(int code) {
     case RN_E_UNSUPPORTED: return "unsupported network (reaction order above 2, or too large)";
     case RN_E_NOMEM: return "out of memory";
     case RN_E_DEVICE: return "HIP device error";
+    case RN_E_SCRATCH: return "input too large for the fixed scratch of an allocation-free call";
     default: return "unknown error";
   }
 }
@@ -402,6 +403,7 @@ namespace rn {
 // rn_hybrid.hip: the rate-equation sweep on the wave-per-trajectory kernel;
 // false (nothing launched) when the network does not fit it.
 bool launch_ode_wave(const HybridParams& p, hipStream_t stream, hipError_t* err);
+bool ode_wave_fits(int n_species, int m_real);
 }  // namespace rn
 
 namespace rn_internal {
@@ -617,21 +619,32 @@ int64_t rn_ode_work_doubles(const rn_network* net, int64_t n_traj) {
   return (int64_t)rn::kOdeSlots * net->N * n_traj;
 }
 
-int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) {
+}  // extern "C"
+
+namespace rn_internal {
+
+// rn_ode_sweep and rn_ode_sweep_noalloc: validate, then run the wave kernel
+// (networks of up to 64 species, no workspace) or the lane kernel on `work`
+// (work == null: the library's fixed scratch, RN_E_SCRATCH if it is too small).
+static int ode_enqueue(const rn_network* net, const rn_ode_args* a, double* work,
+                       int64_t work_ld, hipStream_t stream) {
   if (!net || !a) return RN_E_INVALID_ARG;
   if (a->n_traj < 0 || a->n_traj > ((int64_t)1 << 32) || a->n_times < 1) return RN_E_INVALID_ARG;
   if (!(a->rtol > 0.0) || !std::isfinite(a->rtol) || !(a->atol > 0.0) || !std::isfinite(a->atol))
     return RN_E_INVALID_ARG;
   if (a->max_steps < 1) return RN_E_INVALID_ARG;
   if (a->n_traj == 0) return RN_OK;
-  if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats || !a->work) return RN_E_INVALID_ARG;
-  if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj || a->work_ld < a->n_traj)
-    return RN_E_INVALID_ARG;
+  if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats) return RN_E_INVALID_ARG;
+  if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj) return RN_E_INVALID_ARG;
+  if (work && work_ld < a->n_traj) return RN_E_INVALID_ARG;
   if (a->x0_ld != 0 && a->x0_ld < a->n_traj) return RN_E_INVALID_ARG;
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_error(e);
   if (dev != net->device) return RN_E_INVALID_ARG;
+  const bool wave = rn::ode_wave_fits(net->N, net->dev.M_real);
+  if (!wave && !work && (int64_t)rn::kOdeSlots * net->N * a->n_traj > rn::kOdeScratchDoubles)
+    return RN_E_SCRATCH;
   rn::OdeParams p{};
   p.net = net->dev;
   p.rates = a->rates;
@@ -643,35 +656,61 @@ int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) 
   p.out = a->out;
   p.out_ld = a->out_ld;
   p.stats = a->stats;
-  p.work = a->work;
-  p.work_ld = a->work_ld;
+  p.work = work;
+  p.work_ld = work_ld;
   p.n_traj = a->n_traj;
   p.rtol = a->rtol;
   p.atol = a->atol;
   p.max_steps = a->max_steps;
-  e = rn_internal::stage_network(net, (hipStream_t)hip_stream);
-  if (e == hipSuccess) {
-    // networks of up to 64 species: one wave per trajectory, state in registers
-    rn::HybridParams hp{};
-    hp.net = p.net;
-    hp.rates = p.rates;
-    hp.rates_ld = p.rates_ld;
-    hp.x0 = p.x0;
-    hp.x0_ld = p.x0_ld;
-    hp.times = p.times;
-    hp.n_times = p.n_times;
-    hp.out = p.out;
-    hp.out_ld = p.out_ld;
-    hp.stats = p.stats;
-    hp.n_traj = p.n_traj;
-    hp.rtol = p.rtol;
-    hp.atol = p.atol;
-    hp.max_steps = p.max_steps;
-    if (!rn::launch_ode_wave(hp, (hipStream_t)hip_stream, &e))
-      e = rn::launch_ode(p, (hipStream_t)hip_stream);
+  e = stage_network(net, stream);
+  if (e != hipSuccess) return device_error(e);
+  // networks of up to 64 species: one wave per trajectory, state in registers
+  rn::HybridParams hp{};
+  hp.net = p.net;
+  hp.rates = p.rates;
+  hp.rates_ld = p.rates_ld;
+  hp.x0 = p.x0;
+  hp.x0_ld = p.x0_ld;
+  hp.times = p.times;
+  hp.n_times = p.n_times;
+  hp.out = p.out;
+  hp.out_ld = p.out_ld;
+  hp.stats = p.stats;
+  hp.n_traj = p.n_traj;
+  hp.rtol = p.rtol;
+  hp.atol = p.atol;
+  hp.max_steps = p.max_steps;
+  if (rn::launch_ode_wave(hp, stream, &e)) {
+    if (e != hipSuccess) return device_error(e);
+    return RN_OK;
   }
+  if (!p.work) {
+    e = rn::ode_scratch(&p.work);
+    if (e != hipSuccess) return device_error(e);
+    p.work_ld = p.n_traj;
+  }
+  e = rn::launch_ode(p, stream);
   if (e != hipSuccess) return device_error(e);
   return RN_OK;
+}
+
+}  // namespace rn_internal
+
+extern "C" {
+
+int rn_ode_sweep(const rn_network* net, const rn_ode_args* a, void* hip_stream) {
+  if (!a || (a->n_traj != 0 && !a->work)) return RN_E_INVALID_ARG;
+  return rn_internal::ode_enqueue(net, a, a->work, a->work_ld, (hipStream_t)hip_stream);
+}
+
+int rn_ode_sweep_noalloc(const rn_network* net, const rn_ode_args* a, void* hip_stream) {
+  return rn_internal::ode_enqueue(net, a, nullptr, 0, (hipStream_t)hip_stream);
+}
+
+int64_t rn_ode_noalloc_max_traj(const rn_network* net) {
+  if (!net) return -1;
+  if (rn::ode_wave_fits(net->N, net->dev.M_real)) return (int64_t)1 << 32;
+  return rn::kOdeScratchDoubles / ((int64_t)rn::kOdeSlots * net->N);
 }
 
 void rn_hybrid_args_init(rn_hybrid_args* a) {

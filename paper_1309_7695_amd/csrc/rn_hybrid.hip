@@ -683,9 +683,13 @@ hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream) {
 // The rate-equation sweep on the wave-per-trajectory kernel (every reaction
 // continuous); false when the network does not fit it (more than 64 species or
 // too many reactions for its LDS), and nothing is launched.
+bool ode_wave_fits(int n_species, int m_real) {
+  return n_species <= kWaveWG && wave_lds_bytes(m_real) <= 65536;
+}
+
 bool launch_ode_wave(const HybridParams& p, hipStream_t stream, hipError_t* err) {
   const size_t lds = wave_lds_bytes(p.net.M_real);
-  if (p.net.N > kWaveWG || lds > 65536) return false;
+  if (!ode_wave_fits(p.net.N, p.net.M_real)) return false;
   *err = hipSuccess;
   for (int64_t off = 0; off < p.n_traj; off += kLaunchChunk) {
     const HybridParams q = sub_range(p, off, std::min(kLaunchChunk, p.n_traj - off));

@@ -140,6 +140,12 @@ inline size_t lds_words_per_lane(int N, int M) {
 hipError_t launch_sweep_f64(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_sweep_f32(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
+// Workspace of the allocation-free rate-equation sweep: a file-scope device
+// array of kOdeScratchDoubles doubles per device (32 MiB), whose address on the
+// current device ode_scratch returns (resolved once per device).
+constexpr int64_t kOdeScratchDoubles = (int64_t)4 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t ode_scratch(double** ptr);
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
                           int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream);

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rn_dopri.h"
 #include "rn_kernel.h"
 
@@ -164,6 +166,30 @@ __global__ __launch_bounds__(kOdeWG) void ode_kernel(const OdeParams p) {
 }
 
 }  // namespace
+
+// The allocation-free form of the sweep keeps the lane kernel's workspace in
+// this file-scope array (one copy per device, held until the process ends).
+// Host code never passes the array's name to a kernel: it resolves the
+// device address once per device with hipGetSymbolAddress and passes that.
+__device__ __align__(256) double scratch[kOdeScratchDoubles];
+
+hipError_t ode_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* dev_ptr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!dev_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    dev_ptr[dev] = (double*)p;
+  }
+  *ptr = dev_ptr[dev];
+  return hipSuccess;
+}
 
 // At most 2^24 trajectories per dispatch (a dispatch holds fewer than 2^32
 // work-items); a larger sweep is enqueued as consecutive ranges.

@@ -22,6 +22,7 @@ RN_E_INVALID_NETWORK = -2
 RN_E_UNSUPPORTED = -3
 RN_E_NOMEM = -4
 RN_E_DEVICE = -5
+RN_E_SCRATCH = -6
 ST_ABSORBED, ST_MAXSTEPS, ST_OVERFLOW = 1, 2, 4
 METHOD_TAULEAP, METHOD_SSA = 0, 1
 FP64, FP32 = 0, 1
@@ -33,7 +34,8 @@ EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_netwo
            "rn_server_create", "rn_server_submit", "rn_server_poll", "rn_server_fetch",
            "rn_server_status", "rn_server_free",
            "rn_moments", "rn_ode_args_init",
-           "rn_ode_work_doubles", "rn_ode_sweep", "rn_hybrid_args_init", "rn_hybrid_work_doubles",
+           "rn_ode_work_doubles", "rn_ode_sweep", "rn_ode_sweep_noalloc",
+           "rn_ode_noalloc_max_traj", "rn_hybrid_args_init", "rn_hybrid_work_doubles",
            "rn_hybrid_sweep", "rn_strerror", "rn_last_device_error"]
 
 
@@ -150,6 +152,10 @@ def lib():
         L.rn_ode_work_doubles.restype = C.c_int64
         L.rn_ode_sweep.argtypes = [C.c_void_p, C.POINTER(OdeArgs), C.c_void_p]
         L.rn_ode_sweep.restype = C.c_int
+        L.rn_ode_sweep_noalloc.argtypes = [C.c_void_p, C.POINTER(OdeArgs), C.c_void_p]
+        L.rn_ode_sweep_noalloc.restype = C.c_int
+        L.rn_ode_noalloc_max_traj.argtypes = [C.c_void_p]
+        L.rn_ode_noalloc_max_traj.restype = C.c_int64
         L.rn_hybrid_args_init.argtypes = [C.POINTER(HybridArgs)]
         L.rn_hybrid_args_init.restype = None
         L.rn_hybrid_work_doubles.argtypes = [C.c_void_p, C.c_int64]
@@ -513,14 +519,19 @@ def moment_stats(sum_x, sum_x2, n_traj):
 def ode_sweep(net: Network, rates, x0, times, out, stats, work, *, rtol=1e-6, atol=1e-6,
               max_steps=10**7, stream=None):
     """Enqueue ``rn_ode_sweep``: ``out`` float64 [S][N][>=T], ``work`` float64 device
-    tensor of at least ``rn_ode_work_doubles`` elements; T from ``stats``."""
+    tensor of at least ``rn_ode_work_doubles`` elements; T from ``stats``.  With
+    ``work=None`` it enqueues ``rn_ode_sweep_noalloc`` instead (the library's
+    fixed scratch, at most ``rn_ode_noalloc_max_traj`` trajectories)."""
     import torch
 
     T = int(stats.shape[0])
-    if out.dtype != torch.float64 or work.dtype != torch.float64 or not work.is_contiguous():
-        raise TypeError("out and work must be float64 (work contiguous)")
-    if work.numel() < lib().rn_ode_work_doubles(net.handle, T):
-        raise ValueError("work is too small")
+    if out.dtype != torch.float64:
+        raise TypeError("out must be float64")
+    if work is not None:
+        if work.dtype != torch.float64 or not work.is_contiguous():
+            raise TypeError("work must be contiguous float64")
+        if work.numel() < lib().rn_ode_work_doubles(net.handle, T):
+            raise ValueError("work is too small")
     if rates.dim() != 2 or rates.stride(1) != 1 or out.dim() != 3 or out.stride(2) != 1 or \
             out.stride(0) != out.shape[1] * out.stride(1) or out.shape[0] != times.numel():
         raise ValueError("rates [M][T] and out [S][N][T] need unit trajectory stride")
@@ -532,12 +543,17 @@ def ode_sweep(net: Network, rates, x0, times, out, stats, work, *, rtol=1e-6, at
     a.times, a.n_times = times.data_ptr(), times.numel()
     a.out, a.out_ld = out.data_ptr(), out.stride(1)
     a.stats = stats.data_ptr()
-    a.work, a.work_ld = work.data_ptr(), T
+    if work is not None:
+        a.work, a.work_ld = work.data_ptr(), T
     a.rtol, a.atol, a.max_steps = float(rtol), float(atol), int(max_steps)
     if stream is None:
         stream = torch.cuda.current_stream(rates.device)
-    _check(lib().rn_ode_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)),
-           "rn_ode_sweep")
+    if work is None:
+        _check(lib().rn_ode_sweep_noalloc(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)),
+               "rn_ode_sweep_noalloc")
+    else:
+        _check(lib().rn_ode_sweep(net.handle, C.byref(a), C.c_void_p(stream.cuda_stream)),
+               "rn_ode_sweep")
 
 
 def ode_run(net_desc, rates, x0, times, *, device="cuda", **kw):

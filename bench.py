@@ -31,18 +31,19 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "rn_net_sweep_synthetic_50x100_fp64_traffic.json")
 
 
-def measured_traffic(kind):
+def measured_traffic(kind, layout="traj"):
     """HBM bytes per launch of the FP64 sweep kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE record (each counter scaled by what it
     reads for a copy of known size), or None when the record is for the other
-    kernel kind or the kernel sources changed since the counters were taken."""
+    kernel kind or sample layout, or the kernel sources changed since the
+    counters were taken."""
     import hashlib
 
     try:
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
-    if rec.get("kind") != kind:
+    if rec.get("kind") != kind or rec.get("out_layout", "sample") != layout:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -111,7 +112,7 @@ def parse():
                     help="fp64: the plain FP64 sweep (the headline form); fp32: RN_FP32")
     ap.add_argument("--workload",
                     choices=("synthetic", "batch", "serve", "phases", "copy", "hybrid", "ode",
-                             "moments", "stiff"),
+                             "ode_stiff", "moments", "stiff", "ssa"),
                     default="synthetic",
                     help="synthetic: the 50x100 sweep of 65,536 trajectories (the headline); "
                          "batch: the uneven batch of 64 networks, batched vs one sweep at a "
@@ -119,14 +120,21 @@ def parse():
                          "phases: per-phase cycle profile of the 50x100 sweep; copy: three 1 GiB "
                          "device copies (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE); "
                          "hybrid: the hybrid (PDMP) sweep of the 50x100 network with low counts; "
-                         "ode: the rate-equation sweep of the 50x100 workload; moments: the "
+                         "ode: the rate-equation sweep of the 50x100 workload; ode_stiff: the "
+                         "stiff 30x80 rate equations by the Rosenbrock method beside the "
+                         "explicit pair; ssa: exact-SSA events/s of the dependency-graph and "
+                         "general kernels; moments: the "
                          "ensemble-moment reduction of a 50x100 sample array; stiff: the stiff "
                          "30x80 sweep in FP64 and FP32 with per-species moment errors")
     ap.add_argument("--hybrid-cpu-sample", type=int, default=32,
                     help="trajectories the oracle runs for the hybrid cpu_baseline")
     ap.add_argument("--ode-cpu-sample", type=int, default=8,
                     help="trajectories the oracle runs for the rate-equation cpu_baseline")
+    ap.add_argument("--out-layout", choices=("traj", "sample"), default="traj",
+                    help="synthetic: layout of the sample array (trajectory-major by default)")
     ap.add_argument("--batch-networks", type=int, default=64)
+    ap.add_argument("--batch-persistent", action="store_true",
+                    help="batch: also time the persistent form, untuned and autotuned")
     ap.add_argument("--serve-jobs", type=int, default=1050)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
     ap.add_argument("--serve-warmup", type=int, default=50, help="jobs left out of latencies")
@@ -423,6 +431,158 @@ def ode_main(args, torch, gen, rn):
     print(json.dumps(result), flush=True)
 
 
+def ssa_main(args, torch, gen, rn):
+    """Exact SSA (RN_METHOD_SSA): events/s of the dependency-graph kernel and of
+    the general network-compiled kernel (RN_SSA_KERNEL=full) on the enzyme
+    workload (1,024 trajectories to t = 100) and the 50x100 network (--n-traj
+    trajectories to t = 0.5).  value = the dependency-graph kernel's events/s on
+    the 50x100 network."""
+    dev = torch.device("cuda:0")
+    cases = [("enzyme_4x3", gen.enzyme_workload()),
+             ("synthetic_50x100", gen.synthetic_workload(n_traj=args.n_traj, t_end=0.5,
+                                                         n_samples=11))]
+    res = {}
+    for name, w in cases:
+        T, N, S = w.n_traj, w.net.n_species, len(w.times)
+        net = rn.Network(w.net)
+        r = torch.from_numpy(w.rates).to(dev)
+        x = torch.from_numpy(w.x0).to(dev)
+        tm = torch.from_numpy(w.times).to(dev)
+        o = torch.empty((S, N, T), dtype=torch.int32, device=dev)
+        st = torch.empty((T, 4), dtype=torch.int64, device=dev)
+        for kern in ("dep", "full"):
+            os.environ["RN_SSA_KERNEL"] = kern
+            wall, kern_ms = _timed(torch, dev, args,
+                                   lambda: rn.sweep(net, r, x, tm, o, st, seed=w.seed,
+                                                    method=rn.METHOD_SSA),
+                                   f"ssa {kern} {name}")
+            ev = int(st.cpu().numpy()[:, 1].sum())
+            res[f"{name}_{kern}"] = {"events_per_sweep": ev,
+                                     "kernel_ms": float(np.mean(kern_ms)),
+                                     "events_per_s": ev / (float(np.mean(kern_ms)) / 1e3)}
+            print(f"[bench] ssa {kern} {name}: {res[f'{name}_{kern}']}", file=sys.stderr,
+                  flush=True)
+    os.environ.pop("RN_SSA_KERNEL", None)
+    main = res["synthetic_50x100_dep"]
+    result = {
+        "metric": "exact SSA events/sec (1 GPU)", "value": main["events_per_s"],
+        "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main["kernel_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "exact SSA, enzyme 4x3 and synthetic 50x100",
+                   "n_traj_50x100": args.n_traj, "t_end_50x100": 0.5},
+        "kernels": res, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def ros4_flops_per_step(net):
+    """Algorithmic FP64 operations of one Rosenbrock 4(3) step of one
+    trajectory: the Jacobian (3 per derivative term, N^2 for W), the pivoted LU
+    factorization (a division per multiplier, a multiply and a subtract per
+    updated entry), four triangular solves (2 per off-diagonal entry, N
+    divisions), three right-hand sides (2 per reaction rate, 2 per (reaction,
+    changed species) entry) and 45 per species for the stage arguments,
+    solution, error and norm."""
+    N, M = net.n_species, net.n_reactions
+    nnz = 0
+    dterms = 0
+    for j in range(M):
+        d = {}
+        for s_, k in net.products[j]:
+            d[s_] = d.get(s_, 0) + k
+        for s_, k in net.reactants[j]:
+            d[s_] = d.get(s_, 0) - k
+        changed = sum(1 for v in d.values() if v != 0)
+        nnz += changed
+        dterms += changed * len(net.reactants[j])
+    lu = sum((N - k - 1) + 2 * (N - k - 1) ** 2 for k in range(N))
+    solves = 4 * (2 * N * (N - 1) + N)
+    return 3 * dterms + N * N + lu + solves + 3 * (2 * M + 2 * nnz) + 45 * N
+
+
+def ode_stiff_main(args, torch, gen, rn):
+    """Stiff rate equations: the 30x80 network with rates over eight decades,
+    --n-traj trajectories to t_end 10 (101 samples), rtol = atol = 1e-6, by the
+    Rosenbrock 4(3) method (timed); one sweep of the same inputs by the
+    Dormand-Prince pair gives its step counts and time for comparison.
+    value = Rosenbrock steps (accepted and rejected) per second."""
+    dev = torch.device("cuda:0")
+    w = gen.stiff_workload(n_traj=args.n_traj)
+    T, M, N, S = w.n_traj, w.net.n_reactions, w.net.n_species, len(w.times)
+    net = rn.Network(w.net)
+    r = torch.from_numpy(w.rates).to(dev)
+    x = torch.from_numpy(w.x0).to(dev)
+    tm = torch.from_numpy(w.times).to(dev)
+    o = torch.empty((S, N, T), dtype=torch.float64, device=dev)
+    st = torch.empty((T, 4), dtype=torch.int64, device=dev)
+    work = torch.empty(rn.lib().rn_ode_work_doubles(net.handle, T), dtype=torch.float64,
+                       device=dev)
+    print(f"[bench] stiff ode {w.name}: T={T} N={N} M={M} S={S}", file=sys.stderr, flush=True)
+    wall, kern_ms = _timed(torch, dev, args,
+                           lambda: rn.ode_sweep(net, r, x, tm, o, st, work, method="ros4"),
+                           "ros4 sweeps")
+    s2 = st.cpu().numpy().view(np.uint64)
+    steps = int(s2[:, 0].sum() + s2[:, 1].sum())
+    ros_out = o.cpu().numpy()
+    kern_s = float(np.mean(kern_ms)) / 1000.0
+    fps = ros4_flops_per_step(w.net)
+    achieved = fps * steps / kern_s
+    # the explicit pair on the same inputs, once
+    o2 = torch.empty_like(o)
+    st2 = torch.empty_like(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rn.ode_sweep(net, r, x, tm, o2, st2, work, method="dopri5")
+    torch.cuda.synchronize()
+    dp_s = time.perf_counter() - t0
+    d2 = st2.cpu().numpy().view(np.uint64)
+    dp_out = o2.cpu().numpy()
+    diff = float((np.abs(ros_out - dp_out) / (1.0 + np.abs(dp_out))).max())
+    print(f"[bench] dopri5 once: {dp_s:.2f} s, accepted mean {d2[:, 0].mean():.0f}",
+          file=sys.stderr, flush=True)
+    result = {
+        "metric": "stiff rate-equation sweep: Rosenbrock step evaluations/sec (1 GPU)",
+        "value": steps * args.steps / wall, "unit": "step-evaluations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} stiff rate equations (Rosenbrock 4(3))", "n_traj": T,
+                   "n_species": N, "n_reactions": M, "t_end": float(w.times[-1]),
+                   "n_samples": S, "rtol": 1e-6, "atol": 1e-6, "step_evaluations": steps,
+                   "accepted_mean": float(s2[:, 0].mean()), "accepted_max": int(s2[:, 0].max()),
+                   "rejected_mean": float(s2[:, 1].mean()),
+                   "status_nonzero": int(np.count_nonzero(s2[:, 3]))},
+        "dopri5_same_inputs": {"sweep_s": dp_s, "accepted_mean": float(d2[:, 0].mean()),
+                               "accepted_max": int(d2[:, 0].max()),
+                               "rejected_mean": float(d2[:, 1].mean()),
+                               "status_nonzero": int(np.count_nonzero(d2[:, 3])),
+                               "max_rel_sample_diff_vs_ros4": diff},
+        "kernel": "ros_wave_kernel (rn_ros.hip, one wave per trajectory)",
+        "latency_ms": {"p50": float(np.percentile(kern_ms, 50)),
+                       "p99": float(np.percentile(kern_ms, 99))},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": None,
+                     "flops_per_step": fps, "kernel_ms": kern_s * 1e3},
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        n = min(args.ode_cpu_sample * 16, T)
+        t1 = time.perf_counter()
+        _, ost = oracle.ode_run(w.net, w.rates, w.x0, w.times, traj_range=(0, n), threads=1,
+                                method="ros4")
+        dt = time.perf_counter() - t1
+        csteps = int(ost[:, 0].sum() + ost[:, 1].sum())
+        cpu = {"value": csteps / dt, "unit": "step-evaluations/s", "cores": 1, "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"trajectories 0..{n - 1} of the same sweep, full horizon, "
+                         f"{csteps} Rosenbrock steps in {dt:.1f} s, one thread"}
+    result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
+
+
 def stiff_main(args, torch, gen, rn):
     """Stiff multiscale sweep: 30 species, 80 reactions, rates logU[1e-6, 1e2],
     a fifth of the species below 10 molecules, --n-traj trajectories to
@@ -644,7 +804,45 @@ def batch_main(args, torch, gen, rn):
         "one_at_a_time": {"value": steps / seq_s, "ms_per_step": seq_s * 1e3},
         "speedup_vs_one_at_a_time": seq_s / bat_s,
     }
+    ref = [(j["out"].cpu().numpy(), j["stats"].cpu().numpy()) for j in jobs]
     batch.close()
+
+    # the persistent form: one work-queue kernel per launch shape, first with
+    # the default shapes, then autotuned
+    def persistent(tune):
+        pb = rn.Batch(persistent=True)
+        for j in jobs:
+            pb.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
+                   seed=j["seed"], **kw)
+        tune_s = 0.0
+        if tune:
+            t = time.perf_counter()
+            pb.tune()
+            torch.cuda.synchronize()
+            tune_s = time.perf_counter() - t
+            print(f"[bench] persistent form tuned in {tune_s:.1f} s", file=sys.stderr,
+                  flush=True)
+        pb.launch()
+        torch.cuda.synchronize()
+        same = all(np.array_equal(j["out"].cpu().numpy(), r[0]) and
+                   np.array_equal(j["stats"].cpu().numpy(), r[1]) for j, r in zip(jobs, ref))
+        ts = []
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pb.launch()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            print(f"[bench] persistent{' tuned' if tune else ''} launch {i + 1}/{args.steps}: "
+                  f"{ts[-1] * 1e3:.0f} ms", file=sys.stderr, flush=True)
+        pb.close()
+        ms = float(np.mean(ts)) * 1e3
+        return {"value": steps / (ms / 1e3), "ms_per_step": ms, "tune_s": tune_s,
+                "identical_to_rn_sweep": bool(same), "speedup_vs_graph": bat_s * 1e3 / ms}
+
+    if args.batch_persistent:
+        result["persistent"] = persistent(False)
+        result["persistent_tuned"] = persistent(True)
     print(json.dumps(result), flush=True)
 
 
@@ -691,6 +889,12 @@ def main():
     if args.workload == "ode":
         ode_main(args, torch, gen, rn)
         return
+    if args.workload == "ode_stiff":
+        ode_stiff_main(args, torch, gen, rn)
+        return
+    if args.workload == "ssa":
+        ssa_main(args, torch, gen, rn)
+        return
     if args.workload == "moments":
         moments_main(args, torch, gen, rn)
         return
@@ -704,9 +908,16 @@ def main():
     rates = torch.from_numpy(w.rates).to(dev)
     x0 = torch.from_numpy(w.x0).to(dev)
     times = torch.from_numpy(w.times).to(dev)
-    out = torch.empty((S, N, T), dtype=torch.int32, device=dev)
+    # trajectory-major samples: each trajectory writes its own contiguous rows
+    # (lanes reach the sample times at different moments, so sample-major rows
+    # are written a few values per store)
+    if args.out_layout == "traj":
+        out = torch.empty((T, S, N), dtype=torch.int32, device=dev)
+    else:
+        out = torch.empty((S, N, T), dtype=torch.int32, device=dev)
     stats = torch.empty((T, 4), dtype=torch.int64, device=dev)
-    kw = dict(seed=w.seed, eps=w.eps, n_c=w.n_c, precision=args.precision)
+    kw = dict(seed=w.seed, eps=w.eps, n_c=w.n_c, precision=args.precision,
+              out_layout=args.out_layout)
     print(f"[bench] workload {w.name}: T={T} N={N} M={M} S={S}", file=sys.stderr, flush=True)
     # Setup, outside every timed step: the library compiles the kernel for this
     # network on first use (hipRTC); do it here and report its cost apart.
@@ -765,6 +976,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name} {args.precision.upper()} plain sweep", "n_traj": T, "n_species": N,
                    "n_reactions": M, "t_end": float(w.times[-1]), "n_samples": S,
+                   "out_layout": ("trajectory-major [T][S][N]" if args.out_layout == "traj"
+                                  else "sample-major [S][N][T]"),
                    "eps": w.eps, "n_c": w.n_c, "seed": w.seed,
                    "steps_per_sweep": steps_per_sweep,
                    "leaps": int(st2[:, 0].sum()), "ssa_events": int(st2[:, 1].sum()),
@@ -818,7 +1031,8 @@ def main():
         result["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                               "peak": PEAK_LANE_OPS / 1e12, "unit": "Tlane-op/s",
                               "frac": achieved / PEAK_LANE_OPS,
-                              "traffic": measured_traffic(kind) if T == 65536 else None,
+                              "traffic": (measured_traffic(kind, args.out_layout) if T == 65536
+                                          else None),
                               "kernel": kernel,
                               "ops_per_step": ops_per_step,
                               "kernel_ms": float(np.mean(kern_ms))}

@@ -42,6 +42,9 @@ extern "C" {
 #define RN_METHOD_TAULEAP 0 /* CGP tau-leaping with critical reactions and SSA bursts */
 #define RN_METHOD_SSA 1     /* exact SSA events only (Gillespie direct method)        */
 
+#define RN_OUT_SAMPLE_MAJOR 0 /* out[(s * N + i) * out_ld + t] */
+#define RN_OUT_TRAJ_MAJOR 1   /* out[t * out_ld + s * N + i]   */
+
 #define RN_FP64 0 /* all of the method's arithmetic in double precision                  */
 #define RN_FP32 1 /* single-precision propensities, SSA events, tau' and Poisson means;
                      double precision for time, the SSA-switch test and the critical race */
@@ -109,8 +112,12 @@ int rn_sample_times(double t_end, int32_t n_points, double *out);
  *  times        device, double[n_times]; must be finite, >= 0 and strictly
  *               increasing (device memory is not inspected on the host; the
  *               Python binding checks it before upload).
- *  out          device, int32, out[(s * n_species + i) * out_ld + t] receives
- *               X_i(times[s]) of trajectory t; out_ld >= n_traj.
+ *  out          device, int32, receives X_i(times[s]) of trajectory t at
+ *               out[(s * n_species + i) * out_ld + t] (out_layout
+ *               RN_OUT_SAMPLE_MAJOR, the default; out_ld >= n_traj) or at
+ *               out[t * out_ld + s * n_species + i] (RN_OUT_TRAJ_MAJOR;
+ *               out_ld >= n_times * n_species).  May be null when fused
+ *               statistics (sum_x, hist below) are requested.
  *  stats        device, uint64[n_traj][4]: accepted leaps, SSA events,
  *               rejected leaps, status bits (RN_ST_*).
  *  eps          leap-condition tolerance (finite, > 0); n_c critical threshold
@@ -171,6 +178,38 @@ typedef struct {
    * kernel when the process environment sets RN_PHASE_TIMERS=1 (a separately
    * compiled kernel; the results are unchanged).  Otherwise left untouched. */
   uint64_t *phase_cycles;
+  /* Fused ensemble statistics (all null: off), the summaries that parameter
+   * sweeps, sensitivity analysis and parameter estimation consume (paper, Aims
+   * and motivation section), accumulated by the sweep kernels as each
+   * trajectory reaches each sample time, so that the [n_times][N][n_traj]
+   * sample array need not be written (out may then be null):
+   *  sum_x    device uint64 [n_times][N]: sum over the call's trajectories of
+   *           X_i(times[s]) (exact);
+   *  sum_x2   device uint64 [n_times][N][2]: the sum of X_i^2 as an unsigned
+   *           128-bit integer (low word, high word; exact).  sum_x and sum_x2
+   *           are given together.  Mean and variance follow as for rn_moments.
+   *  hist     device uint32 [n_times][N][hist_bins]: counts of X_i(times[s])
+   *           in bins of hist_width[i] molecules from hist_lo[i] (device int32
+   *           [N] each, widths >= 1); bin b holds lo + b w <= x < lo + (b+1) w,
+   *           counts below lo go to bin 0 and from lo + hist_bins w on to the
+   *           last bin.  hist_bins >= 1 when hist is set (n_times * N *
+   *           hist_bins < 2^31).
+   * The call sets these arrays to zero before its trajectories run, on the
+   * same stream; a sweep split into trajectory ranges adds the ranges' arrays.
+   * Sums are exact integers, so they equal the sums of the sample array. */
+  uint64_t *sum_x;
+  uint64_t *sum_x2;
+  uint32_t *hist;
+  const int32_t *hist_lo;
+  const int32_t *hist_width;
+  int32_t hist_bins;
+  /* RN_OUT_SAMPLE_MAJOR (0, default) or RN_OUT_TRAJ_MAJOR (1), the layout of
+   * `out` above.  Trajectories reach the sample times at different moments,
+   * so in the sample-major layout the 64 lanes of a wave write their values of
+   * one (sample, species) row at different times, each store covering part of
+   * a cache line; in the trajectory-major layout every trajectory writes its
+   * own contiguous rows, whole lines in sequence. */
+  int32_t out_layout;
 } rn_sweep_args;
 
 /* Defaults: eps 0.03, n_c 10, ssa_factor 10, ssa_burst 100, max_steps 1e8,
@@ -225,6 +264,39 @@ void rn_compile_drain(void);
  */
 typedef struct rn_batch rn_batch;
 int rn_batch_create(rn_batch **out);
+/*
+ * Persistent form of a batch (before its first launch; on = 0 restores the
+ * graph of per-job kernels).  Every job runs the generic kernel body (the same
+ * trajectories as rn_sweep), cut into blocks of one workgroup; the jobs that
+ * share a launch shape (precision, trajectories per workgroup, rate constants
+ * in registers or read from memory, and LDS footprint class) form one device
+ * work queue of (job, block) items, largest jobs first, and one persistent
+ * kernel per shape takes items until its queue is empty.  The kernels are the
+ * branches of the graph that rn_batch_launch records and replays (after a
+ * kernel node that zeroes the queue counters).  A job's shape comes from
+ * rn_batch_tune when its bucket was tuned, else 64-lane workgroups with its
+ * rates in registers when they fit.  The launch allocates the queues once, at
+ * the first rn_batch_launch.  Errors: RN_E_INVALID_ARG (null, or after the
+ * first launch).
+ */
+int rn_batch_persistent(rn_batch *b, int32_t on);
+/*
+ * Autotune the persistent form's launch shapes for the batch's jobs (before
+ * its first launch).  Jobs are bucketed by (precision, species / 8, reactions
+ * / 16, nonzero stoichiometry entries / 32); for every bucket not yet tuned in
+ * this process, the bucket's largest job is timed on `hip_stream` in short
+ * trials (up to 256 trajectories per compute unit, to its sixth sample time)
+ * for every candidate: 64 or 256 trajectories per workgroup, rate constants in
+ * registers or in memory, and wave-scheduling thresholds 0.35, 0.5, 0.65 (the
+ * fraction of a wave's live lanes that must wait for a leap before the leap
+ * phases run); the fastest is kept.  Trials write into the job's own output
+ * and stats arrays (a launch rewrites them) and never touch its fused
+ * statistics.  Choices persist for the process and, when the environment sets
+ * RN_TUNE_CACHE to a file path, are read from and written to that file.
+ * Synchronous; allocates temporary device memory.  Errors: RN_E_INVALID_ARG,
+ * RN_E_DEVICE.
+ */
+int rn_batch_tune(rn_batch *b, void *hip_stream);
 int rn_batch_add(rn_batch *b, const rn_network *net, const rn_sweep_args *args);
 int rn_batch_size(const rn_batch *b);
 int rn_batch_launch(rn_batch *b, void *hip_stream);
@@ -284,6 +356,9 @@ int rn_server_fetch(rn_server *s, int64_t job_id, int32_t *out, uint64_t *stats)
 int rn_server_status(rn_server *s, int64_t *queued, int64_t *running, int64_t *bytes_in_use);
 void rn_server_free(rn_server *s);
 
+#define RN_ODE_DOPRI5 0 /* explicit Dormand-Prince 5(4) pair                            */
+#define RN_ODE_ROS4 1   /* linearly implicit Rosenbrock 4(3) method, for stiff networks */
+
 /*
  * Deterministic sweep: the reaction-rate equations that abundant species follow
  * (paper, Methods section: mean-field ODEs, which agree with the stochastic
@@ -324,9 +399,21 @@ typedef struct {
   int64_t work_ld;
   double rtol, atol;
   uint64_t max_steps;
+  /* RN_ODE_DOPRI5 (default) or RN_ODE_ROS4: the Rosenbrock 4(3) method of
+   * L. F. Shampine, ACM Trans. Math. Softw. 8 (1982) 93 (gamma = 1/2), in the
+   * transformed form of Hairer and Wanner (Solving ODEs II, Sec. IV.7).  Each
+   * step forms the exact Jacobian J of the rate equations at y, factors
+   * W = I/(gamma h) - J by Gaussian elimination with partial pivoting and
+   * solves four linear systems; it is stable on stiff networks (rates spanning
+   * many decades), where the explicit pair needs steps of the fastest time
+   * scale.  Error norm, controller (exponent -1/4) and sample clipping as
+   * above; stats[t][1] counts rejected steps.  Networks of up to 64 species
+   * (one wave per trajectory, W in LDS); others return RN_E_UNSUPPORTED.
+   * `work` is not used. */
+  int32_t method;
 } rn_ode_args;
 
-/* Defaults: rtol 1e-6, atol 1e-6, max_steps 1e7. */
+/* Defaults: rtol 1e-6, atol 1e-6, max_steps 1e7, RN_ODE_DOPRI5. */
 void rn_ode_args_init(rn_ode_args *args);
 
 /* Doubles of workspace rn_ode_sweep needs for n_traj trajectories with

@@ -208,6 +208,43 @@ __device__ __forceinline__ uint32_t poisson(R lam, uint32_t hi, uint32_t lo, uin
   else return poisson_ptrs(ld, traj, n, j, k0, k1, lfact);
 }
 
+// Fused ensemble statistics of one recorded state, counts x[i * stride] for
+// i < n at sample si: exact sums of x and of x^2 (as the sums of its two
+// 32-bit words) and the histogram counts, by device-wide atomic additions
+// (every trajectory of the sweep adds to the same cells, at its own time).
+// Out of line, so that each recording site of a kernel adds one call; the
+// kernel passes the fields rather than its parameter block, whose address
+// would force a private copy of it.
+__device__ __noinline__ void add_stats_row(uint64_t* sum_x, uint64_t* sum_x2, uint32_t* hist,
+                                           const int32_t* hist_lo, const int32_t* hist_width,
+                                           int32_t bins, int n, int si, const int32_t* x,
+                                           int stride) {
+  for (int i = 0; i < n; ++i) {
+    const int32_t v = x[i * stride];
+    const int64_t cell = (int64_t)si * n + i;
+    if (sum_x) {
+      const uint64_t q = (uint64_t)((int64_t)v * (int64_t)v);
+      __hip_atomic_fetch_add(sum_x + cell, (uint64_t)(uint32_t)v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(sum_x2 + 2 * cell, q & 0xffffffffull, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      if (q >> 32)
+        __hip_atomic_fetch_add(sum_x2 + 2 * cell + 1, q >> 32, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (hist) {
+      const int64_t d = (int64_t)v - (int64_t)hist_lo[i];
+      uint32_t b = 0u;
+      if (d > 0) {
+        const uint64_t q = (uint64_t)d / (uint64_t)(uint32_t)hist_width[i];
+        b = q < (uint64_t)bins ? (uint32_t)q : (uint32_t)(bins - 1);
+      }
+      __hip_atomic_fetch_add(hist + cell * bins + b, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // Mass-action combinatorial factor h = A * B (halved for a homodimer, where
 // B = A - 1), each count converted to R (exactly, for double).
 template <typename R>

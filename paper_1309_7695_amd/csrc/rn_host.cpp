@@ -29,6 +29,7 @@ struct rn_network {
   size_t bytes = 0;
   rn::DevNet dev{};
   std::string jit_consts;  // compile-time prelude of the network-compiled kernel, or empty
+  int32_t nnz = 0;         // nonzero net changes (entries of the compact stoichiometry)
   // The device tables are filled by the first launch that uses them, on that
   // launch's stream, from a pinned copy of the table image (see stage_network).
   void* himg = nullptr;
@@ -366,6 +367,7 @@ int rn_load_network(const rn_network_desc* desc, rn_network** out) {
   D.col_ent = (const int2*)(b + o_col_ent);
   D.log_fact = (const double*)(b + o_log_fact);
   D.nu_dense = T.nu_dense.empty() ? nullptr : (const int32_t*)(b + o_nu_dense);
+  net->nnz = T.nu_ptr[net->M];
   if (!T.nu_dense.empty()) {
     try {
       net->jit_consts = jit_constants(T, net->N, net->M);
@@ -392,9 +394,10 @@ void rn_free_network(rn_network* net) {
 // wait = false: use it only if already compiled (else start compiling it in the
 // background and run the generic kernel this time).
 static hipFunction_t network_kernel(const rn_network* net, int32_t precision, int wg,
-                                    bool wait = true) {
+                                    bool wait = true, bool ssa_dep = false) {
   if (net->jit_consts.empty() || !rn::jit_enabled()) return nullptr;
-  const int prec = precision == RN_FP32 ? rn::kJitFP32 : rn::kJitFP64;
+  const int prec = (precision == RN_FP32 ? rn::kJitFP32 : rn::kJitFP64) |
+                   (ssa_dep ? rn::kJitSsaDep : 0);
   return wait ? rn::jit_kernel(net->jit_consts, prec, wg)
               : rn::jit_kernel_nowait(net->jit_consts, prec, wg);
 }
@@ -479,8 +482,18 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
     plan.empty = true;
     return RN_OK;
   }
-  if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats) return RN_E_INVALID_ARG;
-  if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj) return RN_E_INVALID_ARG;
+  // fused statistics: sums given together; a histogram needs its bins
+  if ((a->sum_x == nullptr) != (a->sum_x2 == nullptr)) return RN_E_INVALID_ARG;
+  if (a->hist && (!a->hist_lo || !a->hist_width || a->hist_bins < 1 ||
+                  (int64_t)a->n_times * net->N * a->hist_bins >= ((int64_t)1 << 31)))
+    return RN_E_INVALID_ARG;
+  if (!a->rates || !a->x0 || !a->times || !a->stats) return RN_E_INVALID_ARG;
+  if (!a->out && !a->sum_x && !a->hist) return RN_E_INVALID_ARG;
+  if (a->out_layout != RN_OUT_SAMPLE_MAJOR && a->out_layout != RN_OUT_TRAJ_MAJOR)
+    return RN_E_INVALID_ARG;
+  const int64_t out_min = a->out_layout == RN_OUT_TRAJ_MAJOR ? (int64_t)a->n_times * net->N
+                                                             : a->n_traj;
+  if (a->rates_ld < a->n_traj || (a->out && a->out_ld < out_min)) return RN_E_INVALID_ARG;
   if (a->x0_ld != 0 && a->x0_ld < a->n_traj) return RN_E_INVALID_ARG;
 
   int dev = -1;
@@ -503,6 +516,11 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   else cfg.wg = 64;
   cfg.lds_bytes = per_lane * cfg.wg;
   if (cfg.lds_bytes > (size_t)max_lds) return RN_E_UNSUPPORTED;
+  plan.lane_lds = per_lane;
+  plan.max_segs = cfg.rate_segs;
+  plan.n_species = net->N;
+  plan.n_reactions = net->M;
+  plan.nnz = net->nnz;
 
   plan.net = net;
   rn::SweepParams& p = plan.p;
@@ -529,12 +547,28 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   p.cle_threshold = a->cle_threshold;
   p.theta = sched_theta();
   p.phase_cycles = a->phase_cycles;
+  p.sum_x = a->sum_x;
+  p.sum_x2 = a->sum_x2;
+  p.hist = a->hist;
+  p.hist_lo = a->hist_lo;
+  p.hist_width = a->hist_width;
+  p.hist_bins = a->hist ? a->hist_bins : 0;
+  p.out_traj_major = a->out_layout == RN_OUT_TRAJ_MAJOR ? 1 : 0;
   plan.wg = a->n_traj >= (int64_t)256 * n_cu ? 256 : 64;
-  plan.fn = network_kernel(net, a->precision, plan.wg, wait_compile);
+  // exact SSA: the dependency-graph kernel only when the environment sets
+  // RN_SSA_KERNEL=dep (and its propensities fit the registers); the general
+  // kernel measured faster (a wave recomputes nearly every reaction anyway)
+  const bool fp32 = a->precision == RN_FP32;
+  const char* sk = std::getenv("RN_SSA_KERNEL");
+  const bool ssa_dep = a->method == RN_METHOD_SSA && sk && std::strcmp(sk, "dep") == 0 &&
+                       net->M * (fp32 ? 1 : 2) <= rn::kJitSsaDepMaxWords;
+  plan.fn = network_kernel(net, a->precision, plan.wg, wait_compile, ssa_dep);
   if (plan.fn) {
-    plan.lds = rn::jit_lds_bytes(net->N, net->M, plan.wg);
+    plan.lds = ssa_dep ? rn::jit_ssa_lds_bytes(net->N, net->M, net->nnz, plan.wg, fp32)
+                       : rn::jit_lds_bytes(net->N, net->M, plan.wg, fp32);
     if (plan.lds > (size_t)max_lds) plan.fn = nullptr;
   }
+  plan.ssa_dep = plan.fn && ssa_dep;
   return RN_OK;
 }
 
@@ -546,10 +580,10 @@ static rn::SweepParams sub_range(const rn::SweepParams& p, int64_t off, int64_t 
   q.traj_offset = p.traj_offset + (uint32_t)off;
   q.rates = p.rates + off;
   if (p.x0_ld != 0) q.x0 = p.x0 + off;
-  q.out = p.out + off;
+  if (p.out) q.out = p.out + (p.out_traj_major ? off * p.out_ld : off);
   q.stats = p.stats + 4 * off;
   if (p.phase_cycles) q.phase_cycles = p.phase_cycles + 4 * (off / 64);
-  return q;
+  return q;  // the fused statistics add up over the ranges
 }
 
 // At most 2^24 trajectories per dispatch (a dispatch holds fewer than 2^32
@@ -559,7 +593,9 @@ constexpr int64_t kLaunchChunk = (int64_t)1 << 24;
 
 hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
   if (plan.empty) return hipSuccess;
+  const bool stats = plan.p.sum_x || plan.p.hist;
   hipError_t e = stage_network(plan.net, stream);
+  if (e == hipSuccess && stats) e = rn::launch_stats_zero(plan.p, stream);
   for (int64_t off = 0; e == hipSuccess && off < plan.p.n_traj; off += kLaunchChunk) {
     const rn::SweepParams q =
         sub_range(plan.p, off, std::min(kLaunchChunk, plan.p.n_traj - off));
@@ -567,6 +603,7 @@ hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
     else if (plan.precision == RN_FP32) e = rn::launch_sweep_f32(q, plan.cfg, stream);
     else e = rn::launch_sweep_f64(q, plan.cfg, stream);
   }
+  if (e == hipSuccess && stats) e = rn::launch_stats_finish(plan.p, stream);
   return e;
 }
 
@@ -633,6 +670,8 @@ static int ode_enqueue(const rn_network* net, const rn_ode_args* a, double* work
   if (!(a->rtol > 0.0) || !std::isfinite(a->rtol) || !(a->atol > 0.0) || !std::isfinite(a->atol))
     return RN_E_INVALID_ARG;
   if (a->max_steps < 1) return RN_E_INVALID_ARG;
+  if (a->method != RN_ODE_DOPRI5 && a->method != RN_ODE_ROS4) return RN_E_INVALID_ARG;
+  if (a->method == RN_ODE_ROS4 && !rn::ros_fits(net->N, net->dev.M_real)) return RN_E_UNSUPPORTED;
   if (a->n_traj == 0) return RN_OK;
   if (!a->rates || !a->x0 || !a->times || !a->out || !a->stats) return RN_E_INVALID_ARG;
   if (a->rates_ld < a->n_traj || a->out_ld < a->n_traj) return RN_E_INVALID_ARG;
@@ -642,7 +681,7 @@ static int ode_enqueue(const rn_network* net, const rn_ode_args* a, double* work
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return device_error(e);
   if (dev != net->device) return RN_E_INVALID_ARG;
-  const bool wave = rn::ode_wave_fits(net->N, net->dev.M_real);
+  const bool wave = a->method == RN_ODE_ROS4 || rn::ode_wave_fits(net->N, net->dev.M_real);
   if (!wave && !work && (int64_t)rn::kOdeSlots * net->N * a->n_traj > rn::kOdeScratchDoubles)
     return RN_E_SCRATCH;
   rn::OdeParams p{};
@@ -664,6 +703,11 @@ static int ode_enqueue(const rn_network* net, const rn_ode_args* a, double* work
   p.max_steps = a->max_steps;
   e = stage_network(net, stream);
   if (e != hipSuccess) return device_error(e);
+  if (a->method == RN_ODE_ROS4) {
+    e = rn::launch_ros(p, stream);
+    if (e != hipSuccess) return device_error(e);
+    return RN_OK;
+  }
   // networks of up to 64 species: one wave per trajectory, state in registers
   rn::HybridParams hp{};
   hp.net = p.net;

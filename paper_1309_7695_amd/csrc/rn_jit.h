@@ -9,6 +9,9 @@
 namespace rn {
 
 constexpr int kJitFP64 = 0, kJitFP32 = 1;
+// Added to the precision: the exact-SSA kernel with the reaction dependency
+// graph (sweep_net_ssa) instead of the general one.
+constexpr int kJitSsaDep = 2;
 // Networks whose counts and rates fit the compiled kernel's registers.
 constexpr int kJitMaxSpecies = 63, kJitMaxReactions = 128;
 
@@ -16,11 +19,29 @@ constexpr int kJitMaxSpecies = 63, kJitMaxReactions = 128;
 // 16-byte vectors plus one more, which moves consecutive rows to other banks.
 inline int jit_dense_ld(int n) { return 4 * ((n + 3) / 4) + 4; }
 
-// LDS of one workgroup: the dense matrix [M][jit_dense_ld(N)] and every lane's
-// N-word leap candidate.
-inline size_t jit_lds_bytes(int n, int m, int wg) {
-  return ((size_t)m * jit_dense_ld(n) + (size_t)n * wg) * sizeof(int32_t);
+// LDS of one workgroup: the dense matrix [M][jit_dense_ld(N)], every lane's
+// N-word leap candidate, and each wave's leap draw list (means [16][64],
+// counts [16][64], attempt counters [64], items [8 * 64]).
+inline size_t jit_lds_bytes(int n, int m, int wg, bool fp32) {
+  const size_t wave_words = 16 * 64 * (fp32 ? 1 : 2) + 16 * 64 + 64 + 8 * 64;
+  return ((size_t)m * jit_dense_ld(n) + (size_t)n * wg + (size_t)(wg / 64) * wave_words) *
+         sizeof(int32_t);
 }
+
+// LDS of one workgroup of the dependency-graph SSA kernel: the compact
+// stoichiometry (m + 1 offsets, nnz entries), then per lane n count words and
+// the group start sums of its pick (groups as in ssa_group of the kernel).
+inline size_t jit_ssa_lds_bytes(int n, int m, int nnz, int wg, bool fp32) {
+  const int rw = fp32 ? 1 : 2;
+  int gs = 4;
+  while (gs < m && rw * ((m + gs - 1) / gs - 1) > n) gs *= 2;
+  const int g = (m + gs - 1) / gs;
+  const size_t off = ((size_t)(m + 1 + nnz) + 3) / 4 * 4;
+  return (off + (size_t)n * wg + (size_t)(g - 1) * rw * wg) * sizeof(int32_t);
+}
+// The dependency-graph kernel keeps M propensities in registers: networks
+// with M * (words per value) <= kJitSsaDepMaxWords.
+constexpr int kJitSsaDepMaxWords = 200;
 
 // False when the environment sets RN_JIT=0 (the generic kernels are used).
 bool jit_enabled();

@@ -73,6 +73,16 @@ struct SweepParams {
   // not depend on it.
   float theta;
   uint64_t* phase_cycles;  // optional per-wave phase profile (network-compiled kernel)
+  // Fused ensemble statistics (null: off).  During the sweep sum_x2 holds, per
+  // (sample, species), the sums of the low and of the high 32-bit words of
+  // x^2; a finishing pass turns them into the 128-bit sum.
+  uint64_t* sum_x;     // [n_times * N]
+  uint64_t* sum_x2;    // [n_times * N][2]
+  uint32_t* hist;      // [n_times * N][hist_bins]
+  const int32_t* hist_lo;     // [N]
+  const int32_t* hist_width;  // [N]
+  int32_t hist_bins;
+  int32_t out_traj_major;     // 0: out[(s * N + i) * out_ld + t]; 1: out[t * out_ld + s * N + i]
 };
 
 // Reaction-rate-equation sweep (Dormand-Prince 5(4) per lane).
@@ -121,6 +131,17 @@ struct HybridParams {
   uint64_t max_steps;
 };
 
+// A device work queue of sweep blocks for the persistent batch kernel: item k
+// is (job, block) = items[2k], items[2k + 1], block b of a job covering its
+// trajectories [b * WG, (b + 1) * WG).  `next` counts the items taken; it is
+// zero when the kernel starts.
+struct BatchQueue {
+  const SweepParams* jobs;
+  const int32_t* items;
+  int32_t n_items;
+  uint32_t* next;
+};
+
 #ifndef __HIPCC_RTC__
 // Launch configuration chosen by the host.
 struct LaunchCfg {
@@ -139,6 +160,13 @@ inline size_t lds_words_per_lane(int N, int M) {
 
 hipError_t launch_sweep_f64(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
 hipError_t launch_sweep_f32(const SweepParams& p, const LaunchCfg& cfg, hipStream_t stream);
+// Persistent batch kernels (rn_sweep_f64.hip, rn_sweep_f32.hip): `groups`
+// workgroups take items of q until it is empty; cfg gives the workgroup size,
+// the rate registers and the LDS bytes (at least every job's).
+hipError_t launch_persistent_f64(const BatchQueue& q, const LaunchCfg& cfg, hipStream_t stream,
+                                 int64_t groups);
+hipError_t launch_persistent_f32(const BatchQueue& q, const LaunchCfg& cfg, hipStream_t stream,
+                                 int64_t groups);
 hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
 // Workspace of the allocation-free rate-equation sweep: a file-scope device
 // array of kOdeScratchDoubles doubles per device (32 MiB), whose address on the
@@ -146,9 +174,19 @@ hipError_t launch_ode(const OdeParams& p, hipStream_t stream);
 constexpr int64_t kOdeScratchDoubles = (int64_t)4 << 20;
 constexpr int kMaxDevices = 64;
 hipError_t ode_scratch(double** ptr);
+// Rosenbrock 4(3) rate-equation sweep (rn_ros.hip): one wave per trajectory;
+// ros_fits says whether a network fits it (at most 64 species, W in LDS).
+bool ros_fits(int n_species, int m_real);
+hipError_t launch_ros(const OdeParams& p, hipStream_t stream);
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
                           int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream);
+// Fused statistics of a sweep: zero the arrays before it, and afterwards turn
+// the split word sums of x^2 into 128-bit sums (rn_moments.hip).
+hipError_t launch_stats_zero(const SweepParams& p, hipStream_t stream);
+hipError_t launch_stats_finish(const SweepParams& p, hipStream_t stream);
+// p[0 .. n) = v, by a kernel (rn_moments.hip).
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
 #endif  // __HIPCC_RTC__
 
 }  // namespace rn

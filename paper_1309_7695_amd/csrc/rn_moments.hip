@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rn_kernel.h"
 
 namespace rn {
@@ -91,7 +93,63 @@ __global__ __launch_bounds__(kMomWG) void moments_kernel(const int32_t* __restri
   }
 }
 
+// Fused statistics of a sweep: the arrays start at zero; during the sweep each
+// x^2 sum is kept as the sums A and B of its low and high 32-bit words (each
+// below 2^64 for fewer than 2^32 trajectories), and afterwards
+// A + B * 2^32 is written back as a 128-bit (low, high) pair.
+__global__ void stats_zero_kernel(uint64_t* sum_x, uint64_t* sum_x2, int64_t cells,
+                                  uint32_t* hist, int64_t hcells) {
+  const int64_t n = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cells; k += n) {
+    sum_x[k] = 0u;
+    sum_x2[2 * k] = 0u;
+    sum_x2[2 * k + 1] = 0u;
+  }
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < hcells; k += n)
+    hist[k] = 0u;
+}
+
+__global__ void stats_finish_kernel(uint64_t* sum_x2, int64_t cells) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= cells) return;
+  const uint64_t a = sum_x2[2 * k], b = sum_x2[2 * k + 1];
+  const uint64_t lo = a + (b << 32);
+  sum_x2[2 * k] = lo;
+  sum_x2[2 * k + 1] = (b >> 32) + (lo < a ? 1u : 0u);
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p,
+                     n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_zero(const SweepParams& p, hipStream_t stream) {
+  const int64_t cells = p.sum_x ? (int64_t)p.n_times * p.net.N : 0;
+  const int64_t hcells = p.hist ? (int64_t)p.n_times * p.net.N * p.hist_bins : 0;
+  const int64_t most = cells > hcells ? cells : hcells;
+  if (most == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((most + 255) / 256, 4096);
+  hipLaunchKernelGGL(stats_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p.sum_x,
+                     p.sum_x2, cells, p.hist, hcells);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_finish(const SweepParams& p, hipStream_t stream) {
+  if (!p.sum_x2) return hipSuccess;
+  const int64_t cells = (int64_t)p.n_times * p.net.N;
+  hipLaunchKernelGGL(stats_finish_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0,
+                     stream, p.sum_x2, cells);
+  return hipGetLastError();
+}
 
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,
                           int64_t* sum_x, uint64_t* sum_x2, hipStream_t stream) {

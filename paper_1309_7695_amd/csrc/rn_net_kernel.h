@@ -101,6 +101,20 @@ __device__ __noinline__ uint32_t draw_one(R lam, uint32_t traj, uint32_t n, uint
   return poisson<R>(lam, hi, lo, traj, n, j, k0, k1, lfact, cle);
 }
 
+// Words of one wave's leap draw list: means [16][64] of type R, counts
+// [16][64], attempt counters [64], items [8 * 64].
+template <typename R>
+constexpr int kLeapWaveWords = 16 * 64 * (int)(sizeof(R) / 4) + 16 * 64 + 64 + 8 * 64;
+
+// Group size of the SSA pick: the smallest power of two from 4 whose group
+// start sums (G - 1 values of type R) fit in the lane's N candidate words.
+template <typename R>
+constexpr int ssa_group(int n, int m) {
+  int gs = 4;
+  while (gs < m && (int)(sizeof(R) / 4) * ((m + gs - 1) / gs - 1) > n) gs *= 2;
+  return gs;
+}
+
 template <int WG, typename R>
 __device__ __forceinline__ void sweep_net(const SweepParams& p) {
   constexpr int N = rnnet::N, M = rnnet::M, CW = (M + 31) / 32, DLD = rnnet::DLD;
@@ -122,6 +136,42 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
   for (int k = tid; k < M * DLD; k += WG) lds[k] = p.net.nu_dense[k];
   __syncthreads();
   int32_t* const xn = lds + M * DLD + tid;  // xn[i * WG]
+  // Per wave, after every lane's candidate words: the leap draw list of the
+  // wave (means [16][64] of type R, counts [16][64], the lanes' attempt
+  // counters [64], items [8 * 64]); see the leap attempt.
+  int32_t* const wbase = lds + M * DLD + N * WG + (tid >> 6) * kLeapWaveWords<R>;
+  R* const lamw = (R*)wbase;
+  int32_t* const kres = wbase + 16 * 64 * (int)(sizeof(R) / 4);
+  int32_t* const nl = kres + 16 * 64;
+  int32_t* const items = nl + 64;
+  // The same lane-private words hold, during an SSA event, the running sums of
+  // a0 at the group starts g = 1 .. G-1, each in the lane's words
+  // (g - 1) * RW .. (g - 1) * RW + RW - 1 (RW words per value): groups of GS
+  // reactions, GS the smallest power of two from 4 whose G - 1 sums fit in N
+  // words.  Only the lane's own words: other lanes, and other waves of the
+  // workgroup, may be in a leap with their candidates in theirs.
+  constexpr int GS = ssa_group<R>(N, M), G = (M + GS - 1) / GS;
+  constexpr int RW = (int)(sizeof(R) / 4);
+  auto ps_put = [&](auto gc, R v) {
+    constexpr int g = decltype(gc)::value;
+    if constexpr (RW == 2) {
+      const uint64_t u = __builtin_bit_cast(uint64_t, v);
+      xn[(2 * (g - 1)) * WG] = (int32_t)(uint32_t)u;
+      xn[(2 * (g - 1) + 1) * WG] = (int32_t)(uint32_t)(u >> 32);
+    } else {
+      xn[(g - 1) * WG] = __builtin_bit_cast(int32_t, v);
+    }
+  };
+  auto ps_get = [&](auto gc) -> R {
+    constexpr int g = decltype(gc)::value;
+    if constexpr (RW == 2) {
+      const uint64_t u = (uint64_t)(uint32_t)xn[(2 * (g - 1)) * WG] |
+                         ((uint64_t)(uint32_t)xn[(2 * (g - 1) + 1) * WG] << 32);
+      return __builtin_bit_cast(R, u);
+    } else {
+      return __builtin_bit_cast(R, xn[(g - 1) * WG]);
+    }
+  };
 
   const double* const crate = p.rates + (valid ? tl : 0);
   const int64_t rld = p.rates_ld;
@@ -175,17 +225,36 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
   int mode = valid ? (p.method == 1 ? kSsa : kDecide) : kDone;
   const bool ssa_only = p.method == 1;
 
+  const bool want_out = p.out != nullptr;
+  const bool want_stats = p.sum_x != nullptr || p.hist != nullptr;
   auto record = [&](int si) {
     if (!valid) return;
-    // a fresh copy of the row stride per call keeps the N row offsets from
-    // being hoisted out of the main loop (they would pin 2N scalar registers)
-    int64_t ld = p.out_ld;
-    asm volatile("" : "+s"(ld));
-    int32_t* o = p.out + (int64_t)si * N * ld + tl;
-    sfor<0, N>([&](auto ic) {
-      o[0] = x[decltype(ic)::value];
-      o += ld;
-    });
+    if (want_out) {
+      // a fresh copy of the row stride per call keeps the N row offsets from
+      // being hoisted out of the main loop (they would pin 2N scalar registers)
+      int64_t ld = p.out_ld;
+      asm volatile("" : "+s"(ld));
+      if (p.out_traj_major) {
+        int32_t* o = p.out + tl * ld + (int64_t)si * N;
+        sfor<0, N>([&](auto ic) { o[decltype(ic)::value] = x[decltype(ic)::value]; });
+      } else {
+        int32_t* o = p.out + (int64_t)si * N * ld + tl;
+        sfor<0, N>([&](auto ic) {
+          o[0] = x[decltype(ic)::value];
+          o += ld;
+        });
+      }
+    }
+    if (want_stats) {
+      // the lane's candidate words are free whenever a state is recorded:
+      // stage the counts there for the out-of-line statistics pass
+      sfor<0, N>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        xn[i * WG] = x[i];
+      });
+      add_stats_row(p.sum_x, p.sum_x2, p.hist, p.hist_lo, p.hist_width, p.hist_bins, N, si,
+                    xn, WG);
+    }
   };
   auto record_next = [&]() {
     record(s);
@@ -254,34 +323,57 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
       do {
         if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
         fence();
+        // a0 in index order; the running sum at the start of every group of
+        // GS reactions is kept in the lane's LDS words for the pick below
         R sum = R(0);
-        sfor<0, M>([&](auto jc) { sum = sum + aj(jc); });
+        sfor<0, M>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          if constexpr (j > 0 && j % GS == 0) ps_put(Ix<j / GS>{}, sum);
+          sum = sum + aj(jc);
+        });
         if (sum == R(0)) { finish(kStAbsorbed); break; }
         const Words w = philox10(traj, n, 0u, kStreamEvent, k0, k1);
         const R tau = -Real<R>::log_(R(1) - Real<R>::uni(w.w0, w.w1)) / sum;
         const double tn = t + (double)tau;
-        while (s < S && t_next < tn) record_next();
-        if (s == S) { mode = kDone; break; }
-        fence();
+        // The reaction: the first j whose running sum exceeds r.  The sums do
+        // not decrease, so it lies in the group gp with S_gp <= r < S_gp+1
+        // (S_g the kept sum at group g's start, S_0 = 0, S_G = a0); r >= a0
+        // leaves none (gp = G) and takes the last reaction with a_j > 0.  A
+        // group is evaluated, from its kept start, only when some lane picks
+        // in it; the sums inside it are those of the loop above.
         const R r = Real<R>::uni(w.w2, w.w3) * sum;
-        R acc = R(0);
-        int pick = -1, last = -1;
-        sfor<0, (M + 3) / 4>([&](auto gc) {
-          constexpr int g4 = 4 * decltype(gc)::value;
-          if (__any(pick < 0)) {
-            sfor<g4, (g4 + 4 < M ? g4 + 4 : M)>([&](auto jc) {
+        int gp = 0;
+        sfor<1, G>([&](auto gc) {
+          constexpr int g = decltype(gc)::value;
+          gp += (ps_get(gc) <= r) ? 1 : 0;
+        });
+        if (!(r < sum)) gp = G;
+        fence();
+        int pick = -1;
+        sfor<0, G>([&](auto gc) {
+          constexpr int g = decltype(gc)::value;
+          if (__any(gp == g)) {
+            R acc = R(0);
+            if constexpr (g > 0) acc = ps_get(gc);
+            sfor<g * GS, ((g + 1) * GS < M ? (g + 1) * GS : M)>([&](auto jc) {
               constexpr int j = decltype(jc)::value;
-              // selects, not branches: a lane that has picked keeps its state
-              const bool open = pick < 0;
-              const R a = aj(jc);
-              const R acc2 = acc + a;
-              acc = open ? acc2 : acc;
-              last = (open && a > R(0)) ? j : last;
-              pick = (open && r < acc2) ? j : pick;
+              acc = acc + aj(jc);
+              // a select, not a branch: a lane that has picked keeps its pick
+              pick = (gp == g && pick < 0 && r < acc) ? j : pick;
             });
           }
         });
-        if (pick < 0) pick = last;
+        if (__any(gp == G)) {
+          int last = -1;
+          sfor<0, M>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            last = (gp == G && aj(jc) > R(0)) ? j : last;
+          });
+          if (gp == G) pick = last;
+        }
+        // samples before the event take the pre-event state
+        while (s < S && t_next < tn) record_next();
+        if (s == S) { mode = kDone; break; }
         if (pick < 0) { finish(kStAbsorbed); break; }
         if (add_row(x, 1, pick, false) < 0) {  // a count left the int32 range
           add_row(x, 1, pick, true);
@@ -358,84 +450,131 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
 
     // ---------------- one leap attempt ----------------
     const bool ph_leap = __any(mode == kLeap);
-    if (ph_leap) RN_TB();
-    if (mode == kLeap) {
-      do {
-        if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
-        if (tau_p < p.ssa_factor / a0) {
-          mode = kSsa;
-          burst_left = (uint32_t)p.ssa_burst;
-          break;
-        }
-        uint32_t any_crit = 0;
-        sfor<0, CW>([&](auto wc) { any_crit |= crit[decltype(wc)::value]; });
-        double a0c = 0.0;
-        fence();
-        if (__any(any_crit != 0u)) {
-          sfor<0, M>([&](auto jc) {
-            const double a = (double)aj(jc);
-            a0c = critbit(jc) ? a0c + a : a0c;
-          });
-        }
-        Words ev = {0u, 0u, 0u, 0u};
-        double tau_c = __builtin_inf();
-        if (a0c > 0.0) {
-          ev = philox10(traj, n, 0u, kStreamEvent, k0, k1);
-          tau_c = -log(1.0 - u53(ev.w0, ev.w1)) / a0c;
-        }
-        const double delta = t_next - t;
-        const bool fire = (tau_c <= tau_p) && (tau_c <= delta);
-        const double tau = fire ? tau_c : (tau_p < delta ? tau_p : delta);
-
-        // Candidate counts xn; the additions wrap instead of overflowing, and a
-        // candidate whose sums could leave the int32 range is never used (the
-        // exact path below decides).
-        int32_t xmax = 0;
-        sfor<0, N>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          xn[i * WG] = x[i];
-          xmax = max(xmax, x[i]);
-        });
-        uint64_t kabs = 0;
-        const R taur = (R)tau;
-        // Poisson firings of the non-critical reactions over tau, 16 reactions
-        // at a time: their means go into one fresh register vector, a rolled
-        // loop draws them in pairs (the two reactions of a pair share one
-        // Philox block of the first-uniform stream), then each reaction's
-        // draw is added to the candidate.
-        sfor<0, (M + 15) / 16>([&](auto bc) {
-          constexpr int base = 16 * decltype(bc)::value;
+    if (ph_leap) {
+      RN_TB();
+      // Lanes in leap mode: the switch test, the critical race and the leap
+      // length; `go` marks the lanes that go on to draw.
+      bool go = false, fire = false;
+      Words ev = {0u, 0u, 0u, 0u};
+      double a0c = 0.0, tau = 0.0, delta = 0.0;
+      int32_t xmax = 0;
+      if (mode == kLeap) {
+        do {
+          if (steps() >= p.max_steps) { finish(kStMaxSteps); break; }
+          if (tau_p < p.ssa_factor / a0) {
+            mode = kSsa;
+            burst_left = (uint32_t)p.ssa_burst;
+            break;
+          }
+          uint32_t any_crit = 0;
+          sfor<0, CW>([&](auto wc) { any_crit |= crit[decltype(wc)::value]; });
           fence();
-          const uint32_t cw = crit[base >> 5] >> (base & 31);
-          V16 lam;
-          sfor<0, 16>([&](auto ec) {
-            constexpr int e = decltype(ec)::value;
-            if constexpr (base + e < M) {
-              const R lv = aj(Ix<base + e>{}) * taur;
-              lam[e] = ((cw >> e) & 1u) ? R(0) : lv;
-            } else {
-              lam[e] = R(0);
-            }
+          if (__any(any_crit != 0u)) {
+            sfor<0, M>([&](auto jc) {
+              const double a = (double)aj(jc);
+              a0c = critbit(jc) ? a0c + a : a0c;
+            });
+          }
+          double tau_c = __builtin_inf();
+          if (a0c > 0.0) {
+            ev = philox10(traj, n, 0u, kStreamEvent, k0, k1);
+            tau_c = -log(1.0 - u53(ev.w0, ev.w1)) / a0c;
+          }
+          delta = t_next - t;
+          fire = (tau_c <= tau_p) && (tau_c <= delta);
+          tau = fire ? tau_c : (tau_p < delta ? tau_p : delta);
+          // Candidate counts xn; the additions wrap instead of overflowing,
+          // and a candidate whose sums could leave the int32 range is never
+          // used (the exact path below decides).
+          sfor<0, N>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            xn[i * WG] = x[i];
+            xmax = max(xmax, x[i]);
           });
+          go = true;
+        } while (false);
+      }
+      uint64_t kabs = 0;
+      const R taur = (R)tau;
+      // Poisson firings of the non-critical reactions over tau, 16 reactions
+      // at a time.  The means go into one register vector.  The inversion
+      // draws (means in (0, 10), the two reactions of a pair sharing one
+      // Philox block of the first-uniform stream) are spread over the whole
+      // wave: every (lane, pair) that needs a block becomes an item of a
+      // wave-private LDS list, each lane of the wave draws items in turn, and
+      // the counts go back to their lanes through LDS.  Each draw is the
+      // owner's own arithmetic on the owner's counters, so the results do not
+      // depend on which lane computes them.  Means of 10 and more (PTRS,
+      // Langevin) are drawn by their own lanes.
+      const int wl = tid & 63;
+      const uint32_t traj0 = traj - (uint32_t)wl;  // the wave's first trajectory
+      nl[wl] = (int32_t)n;
+      sfor<0, (M + 15) / 16>([&](auto bc) {
+        constexpr int base = 16 * decltype(bc)::value;
+        fence();
+        const uint32_t cw = crit[base >> 5] >> (base & 31);
+        V16 lam;
+        sfor<0, 16>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          if constexpr (base + e < M) {
+            const R lv = aj(Ix<base + e>{}) * taur;
+            lam[e] = (go && !((cw >> e) & 1u)) ? lv : R(0);
+          } else {
+            lam[e] = R(0);
+          }
+        });
+        uint32_t need = 0u;
+        sfor<0, 8>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          const R l0 = lam[2 * q], l1 = lam[2 * q + 1];
+          const bool nq = (l0 > R(0) && l0 < R(10)) || (l1 > R(0) && l1 < R(10));
+          need |= (nq ? 1u : 0u) << q;
+          lamw[(2 * q) * 64 + wl] = l0;
+          lamw[(2 * q + 1) * 64 + wl] = l1;
+        });
+        int total = 0;
+        sfor<0, 8>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          const bool nq = (need >> q) & 1u;
+          const uint64_t m = __ballot(nq);
+          const int below = (int)__builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (nq) items[total + below] = (wl << 3) | q;
+          total += (int)__popcll(m);
+        });
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll 1
+        for (int b0 = 0; b0 < total; b0 += 64) {
+          const int it = b0 + wl;
+          if (it < total) {
+            const int code = items[it];
+            const int o = code >> 3, q = code & 7;
+            const R l0 = lamw[(2 * q) * 64 + o], l1 = lamw[(2 * q + 1) * 64 + o];
+            const Words w = philox10(traj0 + (uint32_t)o, (uint32_t)nl[o],
+                                     (uint32_t)((base >> 1) + q), kStreamFirst, k0, k1);
+            uint32_t ka = 0u, kb = 0u;
+            if (l0 > R(0) && l0 < R(10)) ka = poisson_inversion<R>(l0, Real<R>::uni(w.w0, w.w1));
+            if (l1 > R(0) && l1 < R(10)) kb = poisson_inversion<R>(l1, Real<R>::uni(w.w2, w.w3));
+            kres[(2 * q) * 64 + o] = (int32_t)ka;
+            kres[(2 * q + 1) * 64 + o] = (int32_t)kb;
+          }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (go) {
           I16 kv;
-          // one reaction per iteration, so the samplers (PTRS inlined) have a
-          // single copy per block; the pair's Philox block is made at even e
-          Words w = {0u, 0u, 0u, 0u};
+          // the lane's own counts back from the list, or its large-mean draws
 #pragma unroll 1
           for (int e = 0; e < 16; ++e) {
             const int je = base + e;
             if (je >= M) break;
             const R le = lam[e];
-            if ((e & 1) == 0) {
-              const R lo = lam[e + 1];
-              w = {0u, 0u, 0u, 0u};
-              if ((le > R(0) && le < R(10)) || (lo > R(0) && lo < R(10)))
-                w = philox10(traj, n, (uint32_t)(je >> 1), kStreamFirst, k0, k1);
-            }
-            const uint32_t hi = (e & 1) ? w.w2 : w.w0;
-            const uint32_t lw = (e & 1) ? w.w3 : w.w1;
-            kv[e] = (int32_t)poisson<R, true>(le, hi, lw, traj, n, (uint32_t)je, k0, k1,
-                                              p.net.log_fact, p.cle_threshold);
+            int32_t k = 0;
+            if (le >= R(10))
+              k = (int32_t)poisson<R, true>(le, 0u, 0u, traj, n, (uint32_t)je, k0, k1,
+                                            p.net.log_fact, p.cle_threshold);
+            else if (le > R(0))
+              k = kres[e * 64 + wl];
+            kv[e] = k;
           }
           sfor<0, 16>([&](auto ec) {
             constexpr int e = decltype(ec)::value, j = base + e;
@@ -451,82 +590,87 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
               }
             }
           });
-        });
-        int jc = -1;
-        if (fire) {
-          fence();
-          const double r = u53(ev.w2, ev.w3) * a0c;
-          double acc = 0.0;
-          int last = -1;
-          sfor<0, (M + 3) / 4>([&](auto gc) {
-            constexpr int g4 = 4 * decltype(gc)::value;
-            if (__any(jc < 0)) {
-              sfor<g4, (g4 + 4 < M ? g4 + 4 : M)>([&](auto jj) {
-                constexpr int j = decltype(jj)::value;
-                const bool open = jc < 0 && critbit(jj);
-                const double a = (double)aj(jj);
-                const double acc2 = acc + a;
-                acc = open ? acc2 : acc;
-                last = (open && a > 0.0) ? j : last;
-                jc = (open && r < acc2) ? j : jc;
-              });
-            }
-          });
-          if (jc < 0) jc = last;
-          if (jc < 0) { finish(kStAbsorbed); break; }
-          add_row(xn, WG, jc, false);  // jc differs between lanes
-          kabs += p.net.nu_abs[jc];
         }
+      });
+      // Lanes that drew: the critical firing, the exact check, accept or reject.
+      if (go) {
+        do {
+          int jc = -1;
+          if (fire) {
+            fence();
+            const double r = u53(ev.w2, ev.w3) * a0c;
+            double acc = 0.0;
+            int last = -1;
+            sfor<0, (M + 3) / 4>([&](auto gc) {
+              constexpr int g4 = 4 * decltype(gc)::value;
+              if (__any(jc < 0)) {
+                sfor<g4, (g4 + 4 < M ? g4 + 4 : M)>([&](auto jj) {
+                  constexpr int j = decltype(jj)::value;
+                  const bool open = jc < 0 && critbit(jj);
+                  const double a = (double)aj(jj);
+                  const double acc2 = acc + a;
+                  acc = open ? acc2 : acc;
+                  last = (open && a > 0.0) ? j : last;
+                  jc = (open && r < acc2) ? j : jc;
+                });
+              }
+            });
+            if (jc < 0) jc = last;
+            if (jc < 0) { finish(kStAbsorbed); break; }
+            add_row(xn, WG, jc, false);  // jc differs between lanes
+            kabs += p.net.nu_abs[jc];
+          }
 
-        bool neg = false, big = false;
-        if ((uint64_t)xmax + kabs <= (uint64_t)INT32_MAX) {
-          // no partial sum can leave the int32 range: the candidate is exact
-          int32_t sg = 0;
-          sfor<0, N>([&](auto ic) { sg |= xn[decltype(ic)::value * WG]; });
-          neg = sg < 0;
-        } else {
-          // exact 64-bit evaluation, species by species, redrawing each k_j
+          bool neg = false, big = false;
+          if ((uint64_t)xmax + kabs <= (uint64_t)INT32_MAX) {
+            // no partial sum can leave the int32 range: the candidate is exact
+            int32_t sg = 0;
+            sfor<0, N>([&](auto ic) { sg |= xn[decltype(ic)::value * WG]; });
+            neg = sg < 0;
+          } else {
+            // exact 64-bit evaluation, species by species, redrawing each k_j
+            sfor<0, N>([&](auto ic) {
+              constexpr int i = decltype(ic)::value;
+              fence();
+              int64_t acc = x[i];
+              sfor<rnnet::COL_PTR[i], rnnet::COL_PTR[i + 1]>([&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                constexpr int j = rnnet::COL_ENT[e][0], v = rnnet::COL_ENT[e][1];
+                int64_t kj;
+                if (critbit(Ix<j>{})) {
+                  kj = (fire && j == jc) ? 1 : 0;
+                } else {
+                  kj = draw_one<R>(aj(Ix<j>{}) * taur, traj, n, (uint32_t)j, k0, k1,
+                                   p.net.log_fact, p.cle_threshold);
+                }
+                acc += kj * (int64_t)v;
+              });
+              if (acc < 0) neg = true;
+              else if (acc > INT32_MAX) big = true;
+            });
+          }
+          if (neg) {
+            tau_p = tau_p * 0.5;
+            n = n + 1;
+            rej = rej + 1;
+            break;  // stays in leap mode
+          }
+          if (big) { finish(kStOverflow); break; }
           sfor<0, N>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            fence();
-            int64_t acc = x[i];
-            sfor<rnnet::COL_PTR[i], rnnet::COL_PTR[i + 1]>([&](auto ec) {
-              constexpr int e = decltype(ec)::value;
-              constexpr int j = rnnet::COL_ENT[e][0], v = rnnet::COL_ENT[e][1];
-              int64_t kj;
-              if (critbit(Ix<j>{})) {
-                kj = (fire && j == jc) ? 1 : 0;
-              } else {
-                kj = draw_one<R>(aj(Ix<j>{}) * taur, traj, n, (uint32_t)j, k0, k1,
-                                 p.net.log_fact, p.cle_threshold);
-              }
-              acc += kj * (int64_t)v;
-            });
-            if (acc < 0) neg = true;
-            else if (acc > INT32_MAX) big = true;
+            x[i] = xn[i * WG];
           });
-        }
-        if (neg) {
-          tau_p = tau_p * 0.5;
+          if (tau == delta) t = t_next;
+          else t = t + tau;
           n = n + 1;
-          rej = rej + 1;
-          break;  // stays in leap mode
-        }
-        if (big) { finish(kStOverflow); break; }
-        sfor<0, N>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          x[i] = xn[i * WG];
-        });
-        if (tau == delta) t = t_next;
-        else t = t + tau;
-        n = n + 1;
-        leaps = leaps + 1;
-        while (s < S && t_next <= t) record_next();
-        if (s == S) { mode = kDone; break; }
-        mode = kDecide;
-      } while (false);
+          leaps = leaps + 1;
+          while (s < S && t_next <= t) record_next();
+          if (s == S) { mode = kDone; break; }
+          mode = kDecide;
+        } while (false);
+      }
+      RN_TE(2);
     }
-    if (ph_leap) RN_TE(2);
   }
 #ifdef RN_NET_TIMERS
   tph[3] = clock64() - tstart;
@@ -543,6 +687,211 @@ __device__ __forceinline__ void sweep_net(const SweepParams& p) {
     st[0] = leaps;
     st[1] = ssa;
     st[2] = rej;
+    st[3] = status;
+  }
+}
+
+// Exact SSA only (the direct method, RN_METHOD_SSA) with a reaction
+// dependency graph: every propensity a_k is kept in a register and, after an
+// event, only the reactions whose reactants the event changed are recomputed
+// (Gibson and Bruck, J. Phys. Chem. A 104, 1876 (2000), use the same graph).
+// a0 is still summed over the kept propensities in index order, and the pick
+// uses the running sums of that order, so events are bit for bit those of the
+// general kernel and of the oracle.  Counts live in lane-private LDS words
+// (the registers hold the propensities and, in accumulation registers, the
+// rates); the fired reaction's entries come from a compact list in LDS.  A
+// wave recomputes a reaction when any of its lanes needs it, so the saving
+// depends on how far the lanes' dependent sets overlap.
+template <int WG, typename R>
+__device__ __forceinline__ void sweep_net_ssa(const SweepParams& p) {
+  constexpr int N = rnnet::N, M = rnnet::M;
+  constexpr int NNZ = rnnet::NU_PTR[M];
+  constexpr int GS = ssa_group<R>(N, M), G = (M + GS - 1) / GS;
+  // LDS: the compact stoichiometry (NU_PTR[M + 1], then NU_ENT as
+  // species | nu << 8), then per lane the counts xs[i * WG] and the group
+  // start sums ps[(g - 1) * WG].
+  extern __shared__ int32_t lds[];
+  const int tid = (int)threadIdx.x;
+  const int64_t tl = (int64_t)blockIdx.x * WG + tid;
+  const bool valid = tl < p.n_traj;
+  const uint32_t traj = p.traj_offset + (uint32_t)tl;
+  uint32_t k0, k1;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(k0) : "s"(p.key0));
+  asm volatile("v_mov_b32 %0, %1" : "=v"(k1) : "s"(p.key1));
+  const int S = p.n_times;
+  const double* __restrict__ times = p.times;
+
+  int32_t* const nptr = lds;
+  int32_t* const nent = lds + (M + 1);
+  for (int k = tid; k <= M; k += WG) nptr[k] = rnnet::NU_PTR[k];
+  for (int k = tid; k < NNZ; k += WG)
+    nent[k] = rnnet::NU_ENT[k][0] | (int32_t)((uint32_t)rnnet::NU_ENT[k][1] << 8);
+  __syncthreads();
+  constexpr int kOff = ((M + 1 + NNZ) + 3) / 4 * 4;
+  int32_t* const xs = lds + kOff + tid;                // xs[i * WG]
+  R* const ps = (R*)(lds + kOff + N * WG) + tid;        // ps[(g - 1) * WG]
+
+  const double* const crate = p.rates + (valid ? tl : 0);
+  const int64_t rld = p.rates_ld;
+  RateRegs<R, M> c;
+  sfor<0, M>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    c.put(j, valid ? (R)crate[(int64_t)j * rld] : R(0));
+  });
+  sfor<0, N>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    int32_t v = 0;
+    if (valid) v = p.x0_ld ? p.x0[(int64_t)i * p.x0_ld + tl] : p.x0[i];
+    xs[i * WG] = v;
+  });
+  // h_j at the LDS counts, formed as the general kernel forms it
+  auto hj = [&](auto jc) -> R {
+    constexpr int j = decltype(jc)::value;
+    constexpr int ia = rnnet::LAW[j][0], ib = rnnet::LAW[j][1];
+    constexpr int db = rnnet::LAW[j][2], dimer = rnnet::LAW[j][3];
+    if constexpr (ia == N) return R(1);
+    else if constexpr (ib == N) return (R)xs[ia * WG];
+    else if constexpr (dimer != 0) {
+      const int32_t xa = xs[ia * WG];
+      return R(0.5) * ((R)xa * (R)(xa + db));
+    } else return (R)xs[ia * WG] * (R)xs[ib * WG];
+  };
+  R a[M];
+  sfor<0, M>([&](auto jc) { a[decltype(jc)::value] = c.get(decltype(jc)::value) * hj(jc); });
+
+  double t = 0.0;
+  double t_next = (valid && S > 0) ? times[0] : 0.0;
+  uint32_t n = 0, status = 0;
+  uint64_t ssa = 0;
+  int s = 0;
+  bool live = valid;
+  auto record = [&](int si) {
+    if (!valid) return;
+    if (p.out) {
+      if (p.out_traj_major) {
+        int32_t* o = p.out + tl * p.out_ld + (int64_t)si * N;
+        sfor<0, N>([&](auto ic) { o[decltype(ic)::value] = xs[decltype(ic)::value * WG]; });
+      } else {
+        int32_t* o = p.out + (int64_t)si * N * p.out_ld + tl;
+        sfor<0, N>([&](auto ic) {
+          o[(int64_t)decltype(ic)::value * p.out_ld] = xs[decltype(ic)::value * WG];
+        });
+      }
+    }
+    if (p.sum_x || p.hist)
+      add_stats_row(p.sum_x, p.sum_x2, p.hist, p.hist_lo, p.hist_width, p.hist_bins, N, si,
+                    xs, WG);
+  };
+  auto record_next = [&]() {
+    record(s);
+    s = s + 1;
+    if (s < S) t_next = times[s];
+  };
+  auto finish = [&](uint32_t why) {
+    status |= why;
+    while (s < S) record(s++);
+    live = false;
+  };
+  if (valid) {
+    while (s < S && t_next <= t) record_next();
+    if (s == S) live = false;
+  }
+
+  while (__any(live)) {
+    if (!live) continue;
+    do {
+      if (ssa >= p.max_steps) { finish(kStMaxSteps); break; }
+      R sum = R(0);
+      sfor<0, M>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j > 0 && j % GS == 0) ps[(j / GS - 1) * WG] = sum;
+        sum = sum + a[j];
+      });
+      if (sum == R(0)) { finish(kStAbsorbed); break; }
+      const Words w = philox10(traj, n, 0u, kStreamEvent, k0, k1);
+      const R tau = -Real<R>::log_(R(1) - Real<R>::uni(w.w0, w.w1)) / sum;
+      const double tn = t + (double)tau;
+      // the pick, as in the general kernel: the group of the first running
+      // sum above r, then the running sums inside it
+      const R r = Real<R>::uni(w.w2, w.w3) * sum;
+      int gp = 0;
+      sfor<1, G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        gp += (ps[(g - 1) * WG] <= r) ? 1 : 0;
+      });
+      if (!(r < sum)) gp = G;
+      int pick = -1;
+      sfor<0, G>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if (__any(gp == g)) {
+          R acc = R(0);
+          if constexpr (g > 0) acc = ps[(g - 1) * WG];
+          sfor<g * GS, ((g + 1) * GS < M ? (g + 1) * GS : M)>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            acc = acc + a[j];
+            pick = (gp == g && pick < 0 && r < acc) ? j : pick;
+          });
+        }
+      });
+      if (__any(gp == G)) {
+        int last = -1;
+        sfor<0, M>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          last = (gp == G && a[j] > R(0)) ? j : last;
+        });
+        if (gp == G) pick = last;
+      }
+      while (s < S && t_next < tn) record_next();
+      if (s == S) { live = false; break; }
+      if (pick < 0) { finish(kStAbsorbed); break; }
+      // apply the event to the counts; the species it changes mark the
+      // reactions to recompute
+      uint32_t chg0 = 0u, chg1 = 0u;
+      int32_t neg = 0;
+      const int e1 = nptr[pick + 1];
+      for (int e = nptr[pick]; e < e1; ++e) {
+        const int32_t ent = nent[e];
+        const int sp = ent & 0xff;
+        const int32_t v = ent >> 8;
+        int32_t& xv = xs[sp * WG];
+        xv = (int32_t)((uint32_t)xv + (uint32_t)v);
+        neg |= xv;
+        if (sp < 32) chg0 |= 1u << sp;
+        else chg1 |= 1u << (sp - 32);
+      }
+      if (neg < 0) {  // a count left the int32 range: undo the event
+        for (int e = nptr[pick]; e < e1; ++e) {
+          const int32_t ent = nent[e];
+          int32_t& xv = xs[(ent & 0xff) * WG];
+          xv = (int32_t)((uint32_t)xv - (uint32_t)(ent >> 8));
+        }
+        finish(kStOverflow);
+        break;
+      }
+      t = tn;
+      n = n + 1;
+      ssa = ssa + 1;
+      sfor<0, M>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int ia = rnnet::LAW[j][0], ib = rnnet::LAW[j][1];
+        if constexpr (ia < N) {
+          constexpr uint64_t mk = (1ull << ia) | (ib < N ? (1ull << ib) : 0ull);
+          const bool dirty = ((chg0 & (uint32_t)mk) | (chg1 & (uint32_t)(mk >> 32))) != 0u;
+          if (__any(dirty)) {
+            const R an = c.get(j) * hj(jc);
+            a[j] = dirty ? an : a[j];
+          }
+        }
+      });
+      while (s < S && t_next <= t) record_next();
+      if (s == S) { live = false; break; }
+    } while (false);
+  }
+  if (valid) {
+    uint64_t* st = p.stats + tl * 4;
+    st[0] = 0u;
+    st[1] = ssa;
+    st[2] = 0u;
     st[3] = status;
   }
 }

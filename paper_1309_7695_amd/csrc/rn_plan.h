@@ -15,7 +15,11 @@ struct SweepPlan {
   hipFunction_t fn = nullptr;  // network-compiled kernel, or null for the generic one
   int wg = 0;                  // workgroup size of the network-compiled kernel
   size_t lds = 0;              // its dynamic LDS bytes
+  bool ssa_dep = false;        // it is the dependency-graph exact-SSA kernel
   rn::LaunchCfg cfg{};         // generic kernel configuration
+  size_t lane_lds = 0;         // generic kernel LDS bytes per lane
+  int max_segs = 0;            // rate register vectors of the generic kernel (0: rates in memory)
+  int32_t n_species = 0, n_reactions = 0, nnz = 0;
   rn::SweepParams p{};
 };
 

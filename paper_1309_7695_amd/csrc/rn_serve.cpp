@@ -293,6 +293,15 @@ int rn_server_submit(rn_server* s, const rn_serve_job* job, int64_t* job_id) {
     return RN_E_NOMEM;
   }
   j->params = job->params;
+  // the server writes the sample array; fused statistics are not served
+  j->params.phase_cycles = nullptr;
+  j->params.sum_x = nullptr;
+  j->params.sum_x2 = nullptr;
+  j->params.hist = nullptr;
+  j->params.hist_lo = nullptr;
+  j->params.hist_width = nullptr;
+  j->params.hist_bins = 0;
+  j->params.out_layout = RN_OUT_SAMPLE_MAJOR;
   // validate the method options now (sizes and pointers are the server's)
   {
     rn_sweep_args a = j->params;

@@ -9,4 +9,9 @@ hipError_t launch_sweep_f32(const SweepParams& p, const LaunchCfg& cfg, hipStrea
   return launch_sweep_prec<float>(p, cfg, stream);
 }
 
+hipError_t launch_persistent_f32(const BatchQueue& q, const LaunchCfg& cfg, hipStream_t stream,
+                                 int64_t groups) {
+  return launch_persistent_prec<float>(q, cfg, stream, groups);
+}
+
 }  // namespace rn

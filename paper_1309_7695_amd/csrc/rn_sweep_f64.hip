@@ -8,4 +8,9 @@ hipError_t launch_sweep_f64(const SweepParams& p, const LaunchCfg& cfg, hipStrea
   return launch_sweep_prec<double>(p, cfg, stream);
 }
 
+hipError_t launch_persistent_f64(const BatchQueue& q, const LaunchCfg& cfg, hipStream_t stream,
+                                 int64_t groups) {
+  return launch_persistent_prec<double>(q, cfg, stream, groups);
+}
+
 }  // namespace rn

@@ -78,13 +78,14 @@ struct PickReg {
 // WG lanes per workgroup.  NSEG > 0: the lane's rate constants are held in
 // 16 * NSEG registers (M <= 16 * NSEG); NSEG == 0: they are read from the rates
 // array.
+// The trajectories [tl0, tl0 + WG) of one sweep, one per lane of the workgroup.
 template <int WG, int NSEG, typename R>
-__global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
+__device__ __forceinline__ void sweep_block(const SweepParams& p, int64_t tl0) {
   extern __shared__ int32_t lds[];
   const DevNet& g = p.net;
   const int N = g.N, M = g.M, NP1 = N + 1;
   const int tid = (int)threadIdx.x;
-  const int64_t tl = (int64_t)blockIdx.x * WG + tid;
+  const int64_t tl = tl0 + tid;
   const bool valid = tl < p.n_traj;
   const uint32_t traj = p.traj_offset + (uint32_t)tl;
   // The Philox key is wave-uniform, but its ten round keys would crowd the
@@ -189,8 +190,18 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
   // workgroup (tl >= n_traj) would alias other trajectories' columns.
   auto record = [&](int si) {
     if (!valid) return;
-    int32_t* o = p.out + (int64_t)si * N * p.out_ld + tl;
-    for (int i = 0; i < N; ++i) o[(int64_t)i * p.out_ld] = xc[i * WG];
+    if (p.out) {
+      if (p.out_traj_major) {
+        int32_t* o = p.out + tl * p.out_ld + (int64_t)si * N;
+        for (int i = 0; i < N; ++i) o[i] = xc[i * WG];
+      } else {
+        int32_t* o = p.out + (int64_t)si * N * p.out_ld + tl;
+        for (int i = 0; i < N; ++i) o[(int64_t)i * p.out_ld] = xc[i * WG];
+      }
+    }
+    if (p.sum_x || p.hist)
+      add_stats_row(p.sum_x, p.sum_x2, p.hist, p.hist_lo, p.hist_width, p.hist_bins, N, si, xc,
+                    WG);
   };
   // Record the current state at sample s and move to the next sample time.
   auto record_next = [&]() {
@@ -518,6 +529,39 @@ __global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
 }
 
 template <int WG, int NSEG, typename R>
+__global__ __launch_bounds__(WG, 1) void sweep_kernel(const SweepParams p) {
+  sweep_block<WG, NSEG, R>(p, (int64_t)blockIdx.x * WG);
+}
+
+// Persistent form for batches: each workgroup takes (job, block) items from a
+// device queue until it is empty, and runs block `block` of job `job` exactly
+// as sweep_kernel's workgroup `block` would.  Job parameters are read through
+// the constant address space, so they land in scalar registers as a kernel
+// argument does.
+typedef const uint32_t __attribute__((address_space(4)))* const_u32_ptr;
+
+template <int WG, int NSEG, typename R>
+__global__ __launch_bounds__(WG, 1) void sweep_persistent(const BatchQueue q) {
+  __shared__ int32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(q.next, 1u);
+    __syncthreads();
+    const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();  // every lane has read the item before it is replaced
+    if (it >= q.n_items) return;
+    const int32_t job = __builtin_amdgcn_readfirstlane(q.items[2 * it]);
+    const int32_t blk = __builtin_amdgcn_readfirstlane(q.items[2 * it + 1]);
+    SweepParams p;
+    static_assert(sizeof(SweepParams) % 4 == 0, "parameter block of whole words");
+    const const_u32_ptr src = (const_u32_ptr)(q.jobs + job);
+    uint32_t* const dst = (uint32_t*)&p;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(SweepParams) / 4); ++k) dst[k] = src[k];
+    sweep_block<WG, NSEG, R>(p, (int64_t)blk * WG);
+  }
+}
+
+template <int WG, int NSEG, typename R>
 hipError_t launch_one(const SweepParams& p, size_t lds, hipStream_t stream, int64_t blocks) {
   hipLaunchKernelGGL((sweep_kernel<WG, NSEG, R>), dim3((unsigned)blocks), dim3(WG), lds, stream,
                      p);
@@ -537,6 +581,40 @@ hipError_t launch_wg(const SweepParams& p, const LaunchCfg& cfg, hipStream_t str
     case 7: return launch_one<WG, 7, R>(p, cfg.lds_bytes, stream, blocks);
     case 8: return launch_one<WG, 8, R>(p, cfg.lds_bytes, stream, blocks);
     case 0: return launch_one<WG, 0, R>(p, cfg.lds_bytes, stream, blocks);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int WG, typename R>
+hipError_t launch_persistent_wg(const BatchQueue& q, const LaunchCfg& cfg, hipStream_t stream,
+                                int64_t groups) {
+#define RN_PERSIST(K)                                                                      \
+  case K:                                                                                  \
+    hipLaunchKernelGGL((sweep_persistent<WG, K, R>), dim3((unsigned)groups), dim3(WG),     \
+                       cfg.lds_bytes, stream, q);                                          \
+    return hipGetLastError();
+  switch (cfg.rate_segs) {
+    RN_PERSIST(0)
+    RN_PERSIST(1)
+    RN_PERSIST(2)
+    RN_PERSIST(3)
+    RN_PERSIST(4)
+    RN_PERSIST(5)
+    RN_PERSIST(6)
+    RN_PERSIST(7)
+    RN_PERSIST(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef RN_PERSIST
+}
+
+template <typename R>
+hipError_t launch_persistent_prec(const BatchQueue& q, const LaunchCfg& cfg, hipStream_t stream,
+                                  int64_t groups) {
+  if (groups <= 0) return hipSuccess;
+  switch (cfg.wg) {
+    case 64: return launch_persistent_wg<64, R>(q, cfg, stream, groups);
+    case 256: return launch_persistent_wg<256, R>(q, cfg, stream, groups);
     default: return hipErrorInvalidValue;
   }
 }

@@ -25,12 +25,15 @@ RN_E_DEVICE = -5
 RN_E_SCRATCH = -6
 ST_ABSORBED, ST_MAXSTEPS, ST_OVERFLOW = 1, 2, 4
 METHOD_TAULEAP, METHOD_SSA = 0, 1
+OUT_SAMPLE_MAJOR, OUT_TRAJ_MAJOR = 0, 1
+LAYOUTS = {"sample": OUT_SAMPLE_MAJOR, "traj": OUT_TRAJ_MAJOR}
 FP64, FP32 = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 EXPORTS = ["rn_load_network", "rn_free_network", "rn_network_species", "rn_network_reactions",
            "rn_sample_times", "rn_sweep_args_init", "rn_sweep", "rn_sweep_kernel_kind", "rn_compile_drain",
-           "rn_batch_create", "rn_batch_add", "rn_batch_size", "rn_batch_launch", "rn_batch_free",
+           "rn_batch_create", "rn_batch_persistent", "rn_batch_tune", "rn_batch_add",
+           "rn_batch_size", "rn_batch_launch", "rn_batch_free",
            "rn_server_create", "rn_server_submit", "rn_server_poll", "rn_server_fetch",
            "rn_server_status", "rn_server_free",
            "rn_moments", "rn_ode_args_init",
@@ -56,7 +59,9 @@ class SweepArgs(C.Structure):
                 ("eps", C.c_double), ("n_c", C.c_int32), ("ssa_factor", C.c_double),
                 ("ssa_burst", C.c_int32), ("max_steps", C.c_uint64),
                 ("method", C.c_int32), ("precision", C.c_int32), ("cle_threshold", C.c_double),
-                ("phase_cycles", C.c_void_p)]
+                ("phase_cycles", C.c_void_p), ("sum_x", C.c_void_p), ("sum_x2", C.c_void_p),
+                ("hist", C.c_void_p), ("hist_lo", C.c_void_p), ("hist_width", C.c_void_p),
+                ("hist_bins", C.c_int32), ("out_layout", C.c_int32)]
 
 
 class ServeJob(C.Structure):
@@ -70,7 +75,11 @@ class OdeArgs(C.Structure):
                 ("x0", C.c_void_p), ("x0_ld", C.c_int64), ("times", C.c_void_p),
                 ("n_times", C.c_int32), ("out", C.c_void_p), ("out_ld", C.c_int64),
                 ("stats", C.c_void_p), ("work", C.c_void_p), ("work_ld", C.c_int64),
-                ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64)]
+                ("rtol", C.c_double), ("atol", C.c_double), ("max_steps", C.c_uint64),
+                ("method", C.c_int32)]
+
+
+ODE_METHODS = {"dopri5": 0, "ros4": 1}
 
 
 class HybridArgs(C.Structure):
@@ -122,6 +131,10 @@ def lib():
         L.rn_compile_drain.restype = None
         L.rn_batch_create.argtypes = [C.POINTER(C.c_void_p)]
         L.rn_batch_create.restype = C.c_int
+        L.rn_batch_persistent.argtypes = [C.c_void_p, C.c_int32]
+        L.rn_batch_persistent.restype = C.c_int
+        L.rn_batch_tune.argtypes = [C.c_void_p, C.c_void_p]
+        L.rn_batch_tune.restype = C.c_int
         L.rn_batch_add.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SweepArgs)]
         L.rn_batch_add.restype = C.c_int
         L.rn_batch_size.argtypes = [C.c_void_p]
@@ -230,39 +243,72 @@ class Network:
 
 def sweep_args(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=0, eps=0.03,
                n_c=10, ssa_factor=10.0, ssa_burst=100, max_steps=10**8, method=METHOD_TAULEAP,
-               cle_threshold=0.0, precision="fp64", phase_cycles=None):
+               cle_threshold=0.0, precision="fp64", phase_cycles=None, sum_x=None, sum_x2=None,
+               hist=None, hist_lo=None, hist_width=None, out_layout="sample"):
     """Check the tensors and marshal an ``rn_sweep_args`` for them.
 
     ``rates`` float64 [M][>=T] (row stride = ld), ``x0`` int32 [N] or [N][>=T],
-    ``times`` float64 [S], ``out`` int32 [S][N][>=T] (last dim stride = ld),
-    ``stats`` uint64/int64 [T][4]; all CUDA (HIP) tensors on the network's
-    device.  T is taken from ``stats``.  ``precision`` is "fp64" or "fp32"
-    (RN_FP64 / RN_FP32)."""
+    ``times`` float64 [S], ``out`` int32 [S][N][>=T] (last dim stride = ld) or
+    None when fused statistics are asked for, ``stats`` uint64/int64 [T][4]; all
+    CUDA (HIP) tensors on the network's device.  T is taken from ``stats``.
+    ``precision`` is "fp64" or "fp32" (RN_FP64 / RN_FP32).  Fused statistics:
+    ``sum_x`` 64-bit [S][N] with ``sum_x2`` 64-bit [S][N][2] (exact sums of x and
+    x^2, the latter as 128-bit low/high words), ``hist`` int32 [S][N][B] with
+    ``hist_lo`` and ``hist_width`` int32 [N] (bin edges per species).
+    ``out_layout="traj"`` takes ``out`` as int32 [>=T][S][N] (each trajectory's
+    samples contiguous) instead of [S][N][>=T]."""
     import torch
 
     if precision not in PRECISIONS:
         raise ValueError("precision must be 'fp64' or 'fp32'")
     T = int(stats.shape[0])
     for name, t in (("rates", rates), ("x0", x0), ("times", times), ("out", out),
-                    ("stats", stats)):
-        if not t.is_cuda:
+                    ("stats", stats), ("sum_x", sum_x), ("sum_x2", sum_x2), ("hist", hist),
+                    ("hist_lo", hist_lo), ("hist_width", hist_width)):
+        if t is not None and not t.is_cuda:
             raise ValueError(f"{name} must be a device tensor")
+    if out is None and sum_x is None and hist is None:
+        raise ValueError("out may be None only when sum_x or hist is given")
     if rates.dtype != torch.float64 or times.dtype != torch.float64:
         raise TypeError("rates and times must be float64")
-    if x0.dtype != torch.int32 or out.dtype != torch.int32:
+    if x0.dtype != torch.int32 or (out is not None and out.dtype != torch.int32):
         raise TypeError("x0 and out must be int32")
     if stats.dtype not in (torch.int64, torch.uint64) or tuple(stats.shape) != (T, 4) or \
             not stats.is_contiguous():
         raise TypeError("stats must be a contiguous 64-bit [T][4] tensor")
     if rates.dim() != 2 or rates.stride(1) != 1 or rates.shape[0] != net.n_reactions:
         raise ValueError("rates must be [M][T] with unit trajectory stride")
-    if out.dim() != 3 or out.stride(2) != 1 or out.shape[1] != net.n_species or \
-            out.stride(0) != out.shape[1] * out.stride(1) or out.shape[0] != times.numel():
+    if out_layout not in LAYOUTS:
+        raise ValueError("out_layout must be 'sample' or 'traj'")
+    traj_major = out_layout == "traj"
+    if out is not None and not traj_major and (
+            out.dim() != 3 or out.stride(2) != 1 or out.shape[1] != net.n_species or
+            out.stride(0) != out.shape[1] * out.stride(1) or out.shape[0] != times.numel()):
         raise ValueError("out must be [S][N][T] with unit trajectory stride")
+    if out is not None and traj_major and (
+            out.dim() != 3 or out.shape[1] != times.numel() or out.shape[2] != net.n_species or
+            out.stride(2) != 1 or out.stride(1) != net.n_species):
+        raise ValueError("out must be [T][S][N] with contiguous [S][N] rows")
     if not times.is_contiguous():
         raise ValueError("times must be contiguous")
-    if rates.shape[1] < T or out.shape[2] < T:
+    if rates.shape[1] < T or (out is not None and out.shape[0 if traj_major else 2] < T):
         raise ValueError("rates and out need at least one column per trajectory")
+    S, N = times.numel(), net.n_species
+    if (sum_x is None) != (sum_x2 is None):
+        raise ValueError("sum_x and sum_x2 go together")
+    if sum_x is not None:
+        if sum_x.dtype not in (torch.int64, torch.uint64) or sum_x.numel() != S * N or \
+                not sum_x.is_contiguous() or sum_x2.dtype not in (torch.int64, torch.uint64) or \
+                sum_x2.numel() != 2 * S * N or not sum_x2.is_contiguous():
+            raise ValueError("sum_x must be 64-bit [S][N] and sum_x2 64-bit [S][N][2], contiguous")
+    bins = 0
+    if hist is not None:
+        if hist.dtype != torch.int32 or hist.numel() % (S * N) != 0 or not hist.is_contiguous():
+            raise ValueError("hist must be a contiguous int32 [S][N][B] tensor")
+        bins = hist.numel() // (S * N)
+        for name, t in (("hist_lo", hist_lo), ("hist_width", hist_width)):
+            if t is None or t.dtype != torch.int32 or t.numel() != N or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous int32 [N] device tensor")
     if x0.dim() == 1:
         x0_ld = 0
         if x0.numel() != net.n_species or not x0.is_contiguous():
@@ -278,8 +324,15 @@ def sweep_args(net: Network, rates, x0, times, out, stats, *, seed, traj_offset=
     a.rates, a.rates_ld = rates.data_ptr(), rates.stride(0)
     a.x0, a.x0_ld = x0.data_ptr(), x0_ld
     a.times, a.n_times = times.data_ptr(), times.numel()
-    a.out, a.out_ld = out.data_ptr(), out.stride(1)
+    a.out_layout = LAYOUTS[out_layout]
+    if out is not None:
+        a.out, a.out_ld = out.data_ptr(), (out.stride(0) if traj_major else out.stride(1))
     a.stats = stats.data_ptr()
+    if sum_x is not None:
+        a.sum_x, a.sum_x2 = sum_x.data_ptr(), sum_x2.data_ptr()
+    if hist is not None:
+        a.hist, a.hist_bins = hist.data_ptr(), bins
+        a.hist_lo, a.hist_width = hist_lo.data_ptr(), hist_width.data_ptr()
     a.seed = int(seed) & (2**64 - 1)
     a.eps, a.n_c, a.ssa_factor = float(eps), int(n_c), float(ssa_factor)
     a.ssa_burst, a.max_steps, a.method, a.precision = int(ssa_burst), int(max_steps), \
@@ -312,16 +365,26 @@ class Batch:
     networks alive.  The first ``launch`` records the graph, later ones replay
     it (rewriting the same output tensors)."""
 
-    def __init__(self):
+    def __init__(self, persistent=False):
         h = C.c_void_p()
         _check(lib().rn_batch_create(C.byref(h)), "rn_batch_create")
         self.handle = h
         self._keep = []
+        if persistent:
+            _check(lib().rn_batch_persistent(self.handle, 1), "rn_batch_persistent")
 
     def add(self, net: Network, rates, x0, times, out, stats, **kw):
         a = sweep_args(net, rates, x0, times, out, stats, **kw)
         _check(lib().rn_batch_add(self.handle, net.handle, C.byref(a)), "rn_batch_add")
-        self._keep.append((net, rates, x0, times, out, stats))
+        self._keep.append((net, rates, x0, times, out, stats, kw))
+
+    def tune(self, stream=None):
+        """``rn_batch_tune``: time the persistent form's launch shapes per bucket."""
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().rn_batch_tune(self.handle, C.c_void_p(stream.cuda_stream)), "rn_batch_tune")
 
     def __len__(self):
         n = lib().rn_batch_size(self.handle)
@@ -517,7 +580,7 @@ def moment_stats(sum_x, sum_x2, n_traj):
 
 
 def ode_sweep(net: Network, rates, x0, times, out, stats, work, *, rtol=1e-6, atol=1e-6,
-              max_steps=10**7, stream=None):
+              max_steps=10**7, method="dopri5", stream=None):
     """Enqueue ``rn_ode_sweep``: ``out`` float64 [S][N][>=T], ``work`` float64 device
     tensor of at least ``rn_ode_work_doubles`` elements; T from ``stats``.  With
     ``work=None`` it enqueues ``rn_ode_sweep_noalloc`` instead (the library's
@@ -546,6 +609,9 @@ def ode_sweep(net: Network, rates, x0, times, out, stats, work, *, rtol=1e-6, at
     if work is not None:
         a.work, a.work_ld = work.data_ptr(), T
     a.rtol, a.atol, a.max_steps = float(rtol), float(atol), int(max_steps)
+    if method not in ODE_METHODS:
+        raise ValueError("method must be 'dopri5' or 'ros4'")
+    a.method = ODE_METHODS[method]
     if stream is None:
         stream = torch.cuda.current_stream(rates.device)
     if work is None:

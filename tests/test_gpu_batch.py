@@ -93,3 +93,105 @@ def test_batch_rejects_jobs_after_launch():
     with pytest.raises(rn.RNError):
         b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=2)
     b.close()
+
+
+def _batch_matches(jobs, ref, b, label, extra=None):
+    import torch
+    for rep in range(3):
+        for j in jobs:  # clear the outputs eagerly, outside the graph
+            j["out"].fill_(-1)
+            j["stats"].zero_()
+        torch.cuda.synchronize()
+        b.launch()
+        torch.cuda.synchronize()
+        for k, j in enumerate(jobs):
+            assert np.array_equal(j["out"].cpu().numpy(), ref[k][0]), (label, rep, k)
+            assert np.array_equal(j["stats"].cpu().numpy(), ref[k][1]), (label, rep, k)
+        if extra is not None:
+            extra(rep)
+        _say(f"{label} replay {rep}: {len(jobs)} jobs identical to rn_sweep")
+        x = torch.randn(1 << 20, device="cuda:0")
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum()).item()
+
+
+def _reference(jobs, **kw):
+    import torch
+    ref = []
+    for j in jobs:
+        rn.sweep(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=j["seed"],
+                 **kw)
+        torch.cuda.synchronize()
+        ref.append((j["out"].cpu().numpy().copy(), j["stats"].cpu().numpy().copy()))
+    return ref
+
+
+def test_persistent_batch_equals_individual_sweeps_over_replays():
+    # one persistent kernel per launch shape over a (job, block) queue; every
+    # job bit for bit the trajectories rn_sweep gives (network-compiled or not)
+    jobs = _jobs()
+    ref = _reference(jobs)
+    b = rn.Batch(persistent=True)
+    for j in jobs:
+        b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=j["seed"])
+    _batch_matches(jobs, ref, b, "persistent")
+    b.close()
+
+
+def test_persistent_batch_fp32_and_fused_statistics():
+    import torch
+    jobs = _jobs()[:3]
+    ref = _reference(jobs, precision="fp32")
+    dev = torch.device("cuda:0")
+    sums = []
+    b = rn.Batch(persistent=True)
+    for j in jobs:
+        S, N = len(j["w"].times), j["w"].net.n_species
+        sx = torch.zeros((S, N), dtype=torch.int64, device=dev)
+        sq = torch.zeros((S, N, 2), dtype=torch.int64, device=dev)
+        sums.append((sx, sq))
+        b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=j["seed"],
+              precision="fp32", sum_x=sx, sum_x2=sq)
+
+    def check_sums(rep):
+        for k, j in enumerate(jobs):
+            o = ref[k][0].astype(np.int64)
+            assert np.array_equal(sums[k][0].cpu().numpy(), o.sum(axis=2)), (rep, k)
+            q = sums[k][1].cpu().numpy().view(np.uint64)
+            got = [int(a) + (int(c) << 64) for a, c in zip(q[..., 0].ravel(), q[..., 1].ravel())]
+            want = [int(v) for v in (o * o).sum(axis=2).ravel()]
+            assert got == want, (rep, k)
+
+    _batch_matches(jobs, ref, b, "persistent fp32 + statistics", check_sums)
+    b.close()
+
+
+def test_tuned_persistent_batch_and_cache_file(tmp_path, monkeypatch):
+    # the autotuner's choices change launch shapes only: results stay those of
+    # rn_sweep; the choices are written to RN_TUNE_CACHE
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RN_TUNE_CACHE", str(cache))
+    jobs = _jobs()
+    ref = _reference(jobs)
+    b = rn.Batch(persistent=True)
+    for j in jobs:
+        b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=j["seed"])
+    b.tune()
+    lines = cache.read_text().split("\n")
+    rows = [l.split() for l in lines if l.strip()]
+    _say(f"tuned buckets: {rows}")
+    assert rows and all(len(r) == 7 and r[4] in ("64", "256") for r in rows)
+    _batch_matches(jobs, ref, b, "tuned persistent")
+    b.close()
+
+
+def test_persistent_switch_rejected_after_launch():
+    import torch
+    j = _jobs()[0]
+    b = rn.Batch()
+    b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=1)
+    b.launch()
+    torch.cuda.synchronize()
+    assert rn.lib().rn_batch_persistent(b.handle, 1) == rn.RN_E_INVALID_ARG
+    assert rn.lib().rn_batch_tune(b.handle, None) == rn.RN_E_INVALID_ARG
+    b.close()

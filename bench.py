@@ -816,6 +816,7 @@ def batch_main(args, torch, gen, rn):
                    seed=j["seed"], **kw)
         tune_s = 0.0
         if tune:
+            os.environ.setdefault("RN_TUNE_LOG", "1")  # a line per bucket: progress
             t = time.perf_counter()
             pb.tune()
             torch.cuda.synchronize()

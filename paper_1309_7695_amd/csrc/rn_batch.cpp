@@ -398,6 +398,10 @@ int rn_batch_tune(rn_batch* b, void* hip_stream) {
       if (it == todo.end() || b->work[i] > b->work[it->second]) todo[k] = i;
     }
   }
+  // RN_TUNE_LOG=1: one line per bucket on stderr as it is tuned
+  const char* lg = std::getenv("RN_TUNE_LOG");
+  const bool log = lg && lg[0] == '1';
+  size_t done = 0;
   for (const auto& kv : todo) {
     const rn_internal::SweepPlan& pl = b->plans[kv.second];
     // a trial: up to one wave per SIMD of trajectories, to the 6th sample
@@ -409,7 +413,8 @@ int rn_batch_tune(rn_batch* b, void* hip_stream) {
     for (int wg : {64, 256}) {
       for (int segs : {pl.max_segs, 0}) {
         for (float th : {0.35f, 0.5f, 0.65f}) {
-          if (pl.lane_lds * (size_t)wg > 160 * 1024) continue;
+          // the persistent kernel's own item word shares the 160 KiB
+          if (pl.lane_lds * (size_t)wg + 64 > 160 * 1024) continue;
           float ms = 0.0f;
           e = trial(pl, Shape{wg, segs, th}, n, s_max, st, n_cu, &ms);
           if (e != hipSuccess) return rn_internal::device_status(e);
@@ -422,6 +427,10 @@ int rn_batch_tune(rn_batch* b, void* hip_stream) {
         if (pl.max_segs == 0) break;  // only one rate placement
       }
     }
+    if (log)
+      std::fprintf(stderr, "rn_batch_tune: bucket %zu/%zu (N %d, M %d): wg %d, rate vectors %d, "
+                   "theta %.2f, %.2f ms\n", ++done, todo.size(), pl.n_species, pl.n_reactions,
+                   best.wg, best.segs, best.theta, best_ms);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tuned[kv.first] = best;
   }

@@ -113,8 +113,11 @@ __device__ __forceinline__ void sweep_block(const SweepParams& p, int64_t tl0) {
 #pragma unroll
   for (int j = 0; j < RMAX; ++j)
     c[j] = (NSEG > 0 && valid && j < g.M_real) ? (R)crate[(int64_t)j * rld] : R(0);
-  // c_j of the rates array, for the NSEG == 0 form.
-  auto mrate = [&](int j) -> R { return (R)crate[(int64_t)j * rld]; };
+  // c_j of the rates array, for the NSEG == 0 form; the null reactions that
+  // pad M to whole rate vectors have no row there and rate 0, as in the
+  // register form.
+  const int m_real = g.M_real;
+  auto mrate = [&](int j) -> R { return j < m_real ? (R)crate[(int64_t)j * rld] : R(0); };
 
   // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
   auto prop = [&](int j, R cj) -> R {

@@ -195,3 +195,81 @@ def test_persistent_switch_rejected_after_launch():
     assert rn.lib().rn_batch_persistent(b.handle, 1) == rn.RN_E_INVALID_ARG
     assert rn.lib().rn_batch_tune(b.handle, None) == rn.RN_E_INVALID_ARG
     b.close()
+
+
+RATES_FROM_MEMORY = r"""
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np
+import torch
+from paper_1309_7695_amd import gen, rn
+dev = torch.device("cuda:0")
+ws = [gen.synthetic_workload(n_traj=300, t_end=2.0, n_samples=7, seed=3301),
+      gen.synthetic_workload(n_traj=130, n_species=18, n_reactions=37, t_end=3.0, n_samples=6,
+                             seed=3302)]
+for prec in ("fp64", "fp32"):
+    jobs, ref = [], []
+    for k, w in enumerate(ws):
+        net = rn.Network(w.net)
+        S, N, T = len(w.times), w.net.n_species, w.n_traj
+        j = dict(net=net, rates=torch.from_numpy(w.rates).to(dev),
+                 x0=torch.from_numpy(w.x0).to(dev),
+                 times=torch.from_numpy(w.times).to(dev),
+                 out=torch.full((S, N, T), -1, dtype=torch.int32, device=dev),
+                 stats=torch.zeros((T, 4), dtype=torch.int64, device=dev), seed=91 + k)
+        rn.sweep(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=j["seed"],
+                 precision=prec)
+        torch.cuda.synchronize()
+        ref.append((j["out"].cpu().numpy().copy(), j["stats"].cpu().numpy().copy()))
+        j["out"].fill_(-1)
+        j["stats"].zero_()
+        jobs.append(j)
+    b = rn.Batch(persistent=True)
+    for j in jobs:
+        b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"], seed=j["seed"],
+              precision=prec)
+    b.launch()
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        assert np.array_equal(j["out"].cpu().numpy(), ref[k][0]), (prec, k)
+        assert np.array_equal(j["stats"].cpu().numpy(), ref[k][1]), (prec, k)
+    b.close()
+    print("identical", prec, flush=True)
+"""
+
+
+def _bucket(w, precision):
+    # (precision, species/8, reactions/16, nonzero net changes/32): the tuner's key
+    nnz = 0
+    for re, pr in zip(w.net.reactants, w.net.products):
+        d = {}
+        for s, c in re:
+            d[s] = d.get(s, 0) - c
+        for s, c in pr:
+            d[s] = d.get(s, 0) + c
+        nnz += sum(1 for v in d.values() if v != 0)
+    return (precision, (w.net.n_species + 7) // 8, (w.net.n_reactions + 15) // 16,
+            (nnz + 31) // 32)
+
+
+def test_persistent_rates_from_memory_on_padded_networks(tmp_path):
+    # a tuned shape may read the rate constants from memory (no rate registers)
+    # for a network whose reaction count is padded to whole rate vectors: the
+    # padding reactions have no rows in the rates array and must count as rate
+    # 0, exactly as in the register form
+    import os
+    import subprocess
+    ws = [gen.synthetic_workload(n_traj=300, t_end=2.0, n_samples=7, seed=3301),
+          gen.synthetic_workload(n_traj=130, n_species=18, n_reactions=37, t_end=3.0,
+                                 n_samples=6, seed=3302)]
+    assert all(w.net.n_reactions % 16 for w in ws)
+    cache = tmp_path / "tune.txt"
+    rows = [_bucket(w, p) for w in ws for p in (0, 1)]
+    cache.write_text("".join(f"{a} {b} {c} {d} 64 0 0.500\n" for a, b, c, d in rows))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, RN_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", RATES_FROM_MEMORY.format(root=root)],
+                       capture_output=True, text=True, timeout=300, env=env)
+    _say(r.stdout + r.stderr[-1500:])
+    assert r.returncode == 0
+    assert "identical fp64" in r.stdout and "identical fp32" in r.stdout

@@ -135,6 +135,8 @@ def parse():
     ap.add_argument("--batch-networks", type=int, default=64)
     ap.add_argument("--batch-persistent", action="store_true",
                     help="batch: also time the persistent form, untuned and autotuned")
+    ap.add_argument("--batch-no-sequential", action="store_true",
+                    help="batch: skip the one-sweep-at-a-time timing")
     ap.add_argument("--serve-jobs", type=int, default=1050)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
     ap.add_argument("--serve-warmup", type=int, default=50, help="jobs left out of latencies")
@@ -767,10 +769,12 @@ def batch_main(args, torch, gen, rn):
         batch.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
                   seed=j["seed"], **kw)
     # warm-up: every job once, one at a time (reporting progress), then the graph
-    t = time.perf_counter()
-    sequential(report=True)
-    torch.cuda.synchronize()
-    seq_s = time.perf_counter() - t  # one at a time, FIFO
+    seq_s = None
+    if not args.batch_no_sequential:
+        t = time.perf_counter()
+        sequential(report=True)
+        torch.cuda.synchronize()
+        seq_s = time.perf_counter() - t  # one at a time, FIFO
     batch.launch()
     torch.cuda.synchronize()
     print("[bench] graph recorded", file=sys.stderr, flush=True)
@@ -786,8 +790,8 @@ def batch_main(args, torch, gen, rn):
     bat_s = float(np.mean(bat))
     steps = sum(int(st[:, 0].sum() + st[:, 1].sum()) for st in
                 (j["stats"].cpu().numpy().view(np.uint64) for j in jobs))
-    print(f"[bench] batch {bat_s * 1e3:.1f} ms, one at a time {seq_s * 1e3:.1f} ms",
-          file=sys.stderr, flush=True)
+    print(f"[bench] batch {bat_s * 1e3:.1f} ms, one at a time "
+          f"{seq_s * 1e3 if seq_s else float('nan'):.1f} ms", file=sys.stderr, flush=True)
     result = {
         "metric": "trajectory-steps/sec, uneven batch of 64 networks (1 GPU)",
         "value": steps / bat_s, "unit": "trajectory-steps/s", "n_gpus": 1,
@@ -801,8 +805,9 @@ def batch_main(args, torch, gen, rn):
                    "steps_per_batch": steps},
         "kernels": {"network": kinds.count("network"), "generic": kinds.count("generic")},
         "setup_s": {"kernel_compile": setup_s},
-        "one_at_a_time": {"value": steps / seq_s, "ms_per_step": seq_s * 1e3},
-        "speedup_vs_one_at_a_time": seq_s / bat_s,
+        "one_at_a_time": ({"value": steps / seq_s, "ms_per_step": seq_s * 1e3} if seq_s
+                          else None),
+        "speedup_vs_one_at_a_time": seq_s / bat_s if seq_s else None,
     }
     ref = [(j["out"].cpu().numpy(), j["stats"].cpu().numpy()) for j in jobs]
     batch.close()

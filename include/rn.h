@@ -228,6 +228,11 @@ int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream)
  * network and precision pays the compilation on the calling thread.
  * Returns 1 (network-compiled; compiling it now if needed), 0 (generic), or
  * RN_E_INVALID_ARG / RN_E_DEVICE.
+ * When the environment sets RN_JIT_CACHE to a directory, compiled code objects
+ * are also kept there (one file per network, precision and launch shape,
+ * holding the complete compilation input beside the object; a file is used
+ * only when its stored input equals the current one), so later processes skip
+ * the compilation.
  */
 int rn_sweep_kernel_kind(const rn_network *net, int32_t precision, int64_t n_traj);
 
@@ -285,14 +290,15 @@ int rn_batch_persistent(rn_batch *b, int32_t on);
  * its first launch).  Jobs are bucketed by (precision, species / 8, reactions
  * / 16, nonzero stoichiometry entries / 32); for every bucket not yet tuned in
  * this process, the bucket's largest job is timed on `hip_stream` in short
- * trials (up to 256 trajectories per compute unit, to its sixth sample time)
- * for every candidate: 64 or 256 trajectories per workgroup, rate constants in
- * registers or in memory, and wave-scheduling thresholds 0.35, 0.5, 0.65 (the
- * fraction of a wave's live lanes that must wait for a leap before the leap
- * phases run); the fastest is kept.  Trials write into the job's own output
- * and stats arrays (a launch rewrites them) and never touch its fused
- * statistics.  Choices persist for the process and, when the environment sets
- * RN_TUNE_CACHE to a file path, are read from and written to that file.
+ * trials (up to 256 trajectories per compute unit, each stopped after 400
+ * steps) for every candidate: 64 or 256 trajectories per workgroup, rate
+ * constants in registers or in memory, and wave-scheduling thresholds 0.35,
+ * 0.5, 0.65 (the fraction of a wave's live lanes that must wait for a leap
+ * before the leap phases run); the fastest is kept.  Trials write into the
+ * job's own output and stats arrays (a launch rewrites them) and never touch
+ * its fused statistics.  Choices persist for the process and, when the
+ * environment sets RN_TUNE_CACHE to a file path, are read from and written to
+ * that file; RN_TUNE_LOG=1 prints one line per tuned bucket on stderr.
  * Synchronous; allocates temporary device memory.  Errors: RN_E_INVALID_ARG,
  * RN_E_DEVICE.
  */

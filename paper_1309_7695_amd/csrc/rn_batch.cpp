@@ -315,13 +315,18 @@ hipError_t capture_persistent(rn_batch* b) {
   return hipGraphInstantiate(&b->exec, gph, nullptr, nullptr, 0);
 }
 
-// Time one persistent launch of the trajectories [0, n) of plan `pl`, up to
-// its sample `s_max`, in shape `sh` (without fused statistics); milliseconds.
-hipError_t trial(const rn_internal::SweepPlan& pl, const Shape& sh, int64_t n, int s_max,
+// Steps per trajectory in a tuning trial: every candidate shape runs the same
+// bounded work whatever the job's horizon.
+constexpr uint64_t kTrialSteps = 400;
+
+// Time one persistent launch of the trajectories [0, n) of plan `pl`, each
+// stopped after kTrialSteps steps, in shape `sh` (without fused statistics);
+// milliseconds of the last of `reps` runs.
+hipError_t trial(const rn_internal::SweepPlan& pl, const Shape& sh, int64_t n, int reps,
                  hipStream_t st, int n_cu, float* ms) {
   rn::SweepParams p = pl.p;
   p.n_traj = n;
-  p.n_times = s_max;
+  p.max_steps = std::min<uint64_t>(p.max_steps, kTrialSteps);
   p.theta = sh.theta;
   p.phase_cycles = nullptr;
   p.sum_x = nullptr;
@@ -352,7 +357,7 @@ hipError_t trial(const rn_internal::SweepPlan& pl, const Shape& sh, int64_t n, i
   if (e == hipSuccess) e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&z);
   float best = 0.0f;
-  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the second run is timed
+  for (int rep = 0; rep < reps && e == hipSuccess; ++rep) {
     e = rn::launch_fill_u32(counter, 1, 0u, st);
     if (e == hipSuccess) e = hipEventRecord(a, st);
     if (e == hipSuccess) e = launch_persistent(pl.precision, q, cfg, st, grid);
@@ -404,9 +409,10 @@ int rn_batch_tune(rn_batch* b, void* hip_stream) {
   size_t done = 0;
   for (const auto& kv : todo) {
     const rn_internal::SweepPlan& pl = b->plans[kv.second];
-    // a trial: up to one wave per SIMD of trajectories, to the 6th sample
+    // a trial: up to one wave per SIMD of trajectories; the bucket's first
+    // candidate runs twice (loading its code), the others once
     const int64_t n = std::min<int64_t>(pl.p.n_traj, (int64_t)n_cu * 256);
-    const int s_max = std::min(pl.p.n_times, 6);
+    int reps = 2;
     Shape best{64, pl.max_segs, pl.p.theta};
     float best_ms = 0.0f;
     bool have = false;
@@ -416,7 +422,8 @@ int rn_batch_tune(rn_batch* b, void* hip_stream) {
           // the persistent kernel's own item word shares the 160 KiB
           if (pl.lane_lds * (size_t)wg + 64 > 160 * 1024) continue;
           float ms = 0.0f;
-          e = trial(pl, Shape{wg, segs, th}, n, s_max, st, n_cu, &ms);
+          e = trial(pl, Shape{wg, segs, th}, n, reps, st, n_cu, &ms);
+          reps = 1;
           if (e != hipSuccess) return rn_internal::device_status(e);
           if (!have || ms < best_ms) {
             best = Shape{wg, segs, th};

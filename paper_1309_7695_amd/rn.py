@@ -103,6 +103,15 @@ class RNError(RuntimeError):
 _lib = None
 
 
+def _torch_device_first():
+    """Initialise torch's device state before the library makes its first HIP
+    call: torch initialised only after one of the library's run-time kernel
+    compiles has been seen to report no device."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        torch.cuda.init()
+
+
 def lib():
     """Load ``librn.so``; raises if it has not been built."""
     global _lib
@@ -110,6 +119,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1309_7695_amd.build`")
+        _torch_device_first()
         L = C.CDLL(LIB_PATH)
         L.rn_load_network.argtypes = [C.POINTER(NetworkDesc), C.POINTER(C.c_void_p)]
         L.rn_load_network.restype = C.c_int

@@ -134,9 +134,13 @@ def parse():
                     help="synthetic: layout of the sample array (trajectory-major by default)")
     ap.add_argument("--batch-networks", type=int, default=64)
     ap.add_argument("--batch-persistent", action="store_true",
-                    help="batch: also time the persistent form, untuned and autotuned")
+                    help="batch: time the graph, persistent and tuned forms")
     ap.add_argument("--batch-no-sequential", action="store_true",
                     help="batch: skip the one-sweep-at-a-time timing")
+    ap.add_argument("--batch-forms", default="graph",
+                    help="batch: comma list of graph, persistent, tuned (the first gives value)")
+    ap.add_argument("--batch-seq-precision", choices=("fp64", "fp32"), default=None,
+                    help="batch: precision of the one-at-a-time timing (default --precision)")
     ap.add_argument("--serve-jobs", type=int, default=1050)
     ap.add_argument("--serve-rate", type=float, default=50.0, help="arrivals per second")
     ap.add_argument("--serve-warmup", type=int, default=50, help="jobs left out of latencies")
@@ -726,9 +730,18 @@ def phases_main(args, torch, gen, rn):
 def batch_main(args, torch, gen, rn):
     """Uneven batch: 64 seeded networks of 10-500 reactions (species = reactions/2)
     with 256-16,384 trajectories each, t_end 50, 200 samples.  Times the whole
-    batch as one rn_batch graph launch and as one rn_sweep per network in turn;
-    value = trajectory-steps of the batch / wall time of the graph launch."""
+    batch in the forms --batch-forms names (graph: one rn_batch graph of
+    per-job kernels; persistent: the work-queue kernels in default shapes;
+    tuned: the same after rn_batch_tune) and as one rn_sweep per network in turn
+    (in --batch-seq-precision, default the batch's own); value = trajectory-steps
+    of the batch / wall time of the first form's launch."""
     dev = torch.device("cuda:0")
+    forms = [f for f in args.batch_forms.split(",") if f]
+    if args.batch_persistent:
+        forms = ["graph", "persistent", "tuned"]
+    if not forms or any(f not in ("graph", "persistent", "tuned") for f in forms):
+        raise SystemExit("--batch-forms: a comma list of graph, persistent, tuned")
+    seq_prec = args.batch_seq_precision or args.precision
     ws = gen.batch_workloads(n_networks=args.batch_networks)
     jobs = []
     for k, w in enumerate(ws):
@@ -741,114 +754,122 @@ def batch_main(args, torch, gen, rn):
                          stats=torch.empty((T, 4), dtype=torch.int64, device=dev)))
     t0 = time.perf_counter()
     from concurrent.futures import ThreadPoolExecutor, as_completed
-    kinds = [None] * len(jobs)
+    precs = [args.precision] + ([seq_prec] if seq_prec != args.precision else [])
+    tasks = [(k, pr) for pr in precs for k in range(len(jobs))]
+    kinds = {}
     with ThreadPoolExecutor(max_workers=16) as ex:
-        futs = {ex.submit(rn.sweep_kernel_kind, j["net"], j["T"], args.precision): k
-                for k, j in enumerate(jobs)}
+        futs = {ex.submit(rn.sweep_kernel_kind, jobs[k]["net"], jobs[k]["T"], pr): (k, pr)
+                for k, pr in tasks}
         for n_done, f in enumerate(as_completed(futs), 1):
             kinds[futs[f]] = f.result()
-            print(f"[bench] kernels ready {n_done}/{len(jobs)} "
+            print(f"[bench] kernels ready {n_done}/{len(tasks)} "
                   f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
     setup_s = time.perf_counter() - t0
-    print(f"[bench] batch of {len(jobs)}: {kinds.count('network')} network-compiled, "
-          f"{kinds.count('generic')} generic kernels; setup {setup_s:.1f} s",
+    kind_list = [kinds[(k, args.precision)] for k in range(len(jobs))]
+    print(f"[bench] batch of {len(jobs)}: {kind_list.count('network')} network-compiled, "
+          f"{kind_list.count('generic')} generic kernels; setup {setup_s:.1f} s",
           file=sys.stderr, flush=True)
     kw = dict(precision=args.precision)
 
     def sequential(report=False):
         for k, j in enumerate(jobs):
             rn.sweep(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
-                     seed=j["seed"], **kw)
+                     seed=j["seed"], precision=seq_prec)
             if report:
                 torch.cuda.synchronize()
                 print(f"[bench] job {k + 1}/{len(jobs)} done (M={j['net'].n_reactions}, "
                       f"T={j['T']})", file=sys.stderr, flush=True)
 
-    batch = rn.Batch()
-    for j in jobs:
-        batch.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
-                  seed=j["seed"], **kw)
-    # warm-up: every job once, one at a time (reporting progress), then the graph
-    seq_s = None
+    def count_steps():
+        return sum(int(st[:, 0].sum() + st[:, 1].sum()) for st in
+                   (j["stats"].cpu().numpy().view(np.uint64) for j in jobs))
+
+    # one at a time (also the warm-up of every job's kernel), FIFO
+    seq_s = seq_steps = None
     if not args.batch_no_sequential:
         t = time.perf_counter()
         sequential(report=True)
         torch.cuda.synchronize()
-        seq_s = time.perf_counter() - t  # one at a time, FIFO
-    batch.launch()
-    torch.cuda.synchronize()
-    print("[bench] graph recorded", file=sys.stderr, flush=True)
-    bat = []
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        batch.launch()
-        torch.cuda.synchronize()
-        bat.append(time.perf_counter() - t)
-        print(f"[bench] batch launch {i + 1}/{args.steps}: {bat[-1] * 1e3:.0f} ms",
-              file=sys.stderr, flush=True)
-    bat_s = float(np.mean(bat))
-    steps = sum(int(st[:, 0].sum() + st[:, 1].sum()) for st in
-                (j["stats"].cpu().numpy().view(np.uint64) for j in jobs))
-    print(f"[bench] batch {bat_s * 1e3:.1f} ms, one at a time "
-          f"{seq_s * 1e3 if seq_s else float('nan'):.1f} ms", file=sys.stderr, flush=True)
-    result = {
-        "metric": "trajectory-steps/sec, uneven batch of 64 networks (1 GPU)",
-        "value": steps / bat_s, "unit": "trajectory-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": bat_s * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
-        "config": {"workload": f"uneven batch of {len(jobs)} synthetic networks, "
-                               f"{args.precision.upper()}", "n_networks": len(jobs),
-                   "n_traj_total": int(sum(j["T"] for j in jobs)),
-                   "reactions": [int(j["net"].n_reactions) for j in jobs],
-                   "steps_per_batch": steps},
-        "kernels": {"network": kinds.count("network"), "generic": kinds.count("generic")},
-        "setup_s": {"kernel_compile": setup_s},
-        "one_at_a_time": ({"value": steps / seq_s, "ms_per_step": seq_s * 1e3} if seq_s
-                          else None),
-        "speedup_vs_one_at_a_time": seq_s / bat_s if seq_s else None,
-    }
-    ref = [(j["out"].cpu().numpy(), j["stats"].cpu().numpy()) for j in jobs]
-    batch.close()
+        seq_s = time.perf_counter() - t
+        seq_steps = count_steps()
+        print(f"[bench] one at a time ({seq_prec}): {seq_s * 1e3:.1f} ms", file=sys.stderr,
+              flush=True)
 
-    # the persistent form: one work-queue kernel per launch shape, first with
-    # the default shapes, then autotuned
-    def persistent(tune):
-        pb = rn.Batch(persistent=True)
-        for j in jobs:
-            pb.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
-                   seed=j["seed"], **kw)
-        tune_s = 0.0
-        if tune:
-            os.environ.setdefault("RN_TUNE_LOG", "1")  # a line per bucket: progress
-            t = time.perf_counter()
-            pb.tune()
-            torch.cuda.synchronize()
-            tune_s = time.perf_counter() - t
-            print(f"[bench] persistent form tuned in {tune_s:.1f} s", file=sys.stderr,
-                  flush=True)
-        pb.launch()
+    # every form's results must be those of rn_sweep one at a time (when that ran
+    # in the batch's precision), else those of the first form
+    ref = None
+    if seq_s and seq_prec == args.precision:
+        ref = [(j["out"].cpu().numpy(), j["stats"].cpu().numpy()) for j in jobs]
+
+    def timed(b, label):
+        nonlocal ref
+        t = time.perf_counter()
+        b.launch()  # records the graph; untimed
         torch.cuda.synchronize()
-        same = all(np.array_equal(j["out"].cpu().numpy(), r[0]) and
-                   np.array_equal(j["stats"].cpu().numpy(), r[1]) for j, r in zip(jobs, ref))
+        print(f"[bench] {label} first launch (untimed): {(time.perf_counter() - t) * 1e3:.0f} ms",
+              file=sys.stderr, flush=True)
+        now = [(j["out"].cpu().numpy(), j["stats"].cpu().numpy()) for j in jobs]
+        if ref is None:
+            ref = now
+        same = all(np.array_equal(a[0], r[0]) and np.array_equal(a[1], r[1])
+                   for a, r in zip(now, ref))
         ts = []
         for i in range(args.steps):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            pb.launch()
+            b.launch()
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
-            print(f"[bench] persistent{' tuned' if tune else ''} launch {i + 1}/{args.steps}: "
-                  f"{ts[-1] * 1e3:.0f} ms", file=sys.stderr, flush=True)
-        pb.close()
-        ms = float(np.mean(ts)) * 1e3
-        return {"value": steps / (ms / 1e3), "ms_per_step": ms, "tune_s": tune_s,
-                "identical_to_rn_sweep": bool(same), "speedup_vs_graph": bat_s * 1e3 / ms}
+            print(f"[bench] {label} launch {i + 1}/{args.steps}: {ts[-1] * 1e3:.0f} ms",
+                  file=sys.stderr, flush=True)
+        return float(np.mean(ts)), same
 
-    if args.batch_persistent:
-        result["persistent"] = persistent(False)
-        result["persistent_tuned"] = persistent(True)
+    results = {}
+    steps = None
+    for form in forms:
+        b = rn.Batch(persistent=form != "graph")
+        for j in jobs:
+            b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
+                  seed=j["seed"], **kw)
+        tune_s = 0.0
+        if form == "tuned":
+            os.environ.setdefault("RN_TUNE_LOG", "1")  # a line per bucket: progress
+            t = time.perf_counter()
+            b.tune()
+            torch.cuda.synchronize()
+            tune_s = time.perf_counter() - t
+            print(f"[bench] persistent form tuned in {tune_s:.1f} s", file=sys.stderr,
+                  flush=True)
+        sec, same = timed(b, form)
+        b.close()
+        if steps is None:
+            steps = count_steps()
+        results[form] = {"value": steps / sec, "ms_per_step": sec * 1e3,
+                         "identical_to_reference": bool(same)}
+        if form == "tuned":
+            results[form]["tune_s"] = tune_s
+        if seq_s:
+            results[form]["speedup_vs_one_at_a_time"] = seq_s / sec
+    first = results[forms[0]]
+    result = {
+        "metric": "trajectory-steps/sec, uneven batch of 64 networks (1 GPU)",
+        "value": first["value"], "unit": "trajectory-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": first["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+        "config": {"workload": f"uneven batch of {len(jobs)} synthetic networks, "
+                               f"{args.precision.upper()}, {forms[0]} form",
+                   "n_networks": len(jobs),
+                   "n_traj_total": int(sum(j["T"] for j in jobs)),
+                   "reactions": [int(j["net"].n_reactions) for j in jobs],
+                   "steps_per_batch": steps},
+        "kernels": {"network": kind_list.count("network"),
+                    "generic": kind_list.count("generic")},
+        "setup_s": {"kernel_compile": setup_s},
+        "forms": results,
+        "one_at_a_time": ({"precision": seq_prec, "value": seq_steps / seq_s,
+                           "ms_per_step": seq_s * 1e3} if seq_s else None),
+    }
     print(json.dumps(result), flush=True)
 
 

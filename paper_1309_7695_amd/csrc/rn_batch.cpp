@@ -225,10 +225,15 @@ hipError_t capture_persistent(rn_batch* b) {
   const int n_cu = cu_count(b->device);
   std::vector<Group> groups;
   std::vector<rn::SweepParams> params(b->plans.size());
+  std::vector<size_t> wave_jobs;  // jobs on the one-wave-per-trajectory kernel
   for (size_t i = 0; i < b->plans.size(); ++i) {
     const rn_internal::SweepPlan& pl = b->plans[i];
-    const Shape sh = shape_of(pl);
     params[i] = pl.p;
+    if (pl.wave) {
+      wave_jobs.push_back(i);
+      continue;
+    }
+    const Shape sh = shape_of(pl);
     params[i].theta = sh.theta;
     params[i].phase_cycles = nullptr;
     const int lc = lds_class(pl.lane_lds);
@@ -276,8 +281,14 @@ hipError_t capture_persistent(rn_batch* b) {
   }
   if (e != hipSuccess) return e;
 
+  // the wave jobs on their own branches (at most four), largest first, each to
+  // the branch with the fewest trajectories
+  const int nw = (int)std::min<size_t>(wave_jobs.size(), 4);
+  std::stable_sort(wave_jobs.begin(), wave_jobs.end(), [&](size_t x, size_t y) {
+    return b->work[x] * b->plans[x].n_reactions > b->work[y] * b->plans[y].n_reactions;
+  });
   const int nb = (int)groups.size();
-  for (int k = 0; k < nb + 1; ++k) {
+  for (int k = 0; k < nb + nw + 1; ++k) {
     hipStream_t st = nullptr;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
     b->streams.push_back(st);
@@ -288,9 +299,26 @@ hipError_t capture_persistent(rn_batch* b) {
   hipStream_t origin = b->streams[0];
   if ((e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
   hipError_t err = rn::launch_fill_u32(counters, (int64_t)groups.size(), 0u, origin);
+  // (a wave job's launch_plan zeroes and finishes its own statistics)
   for (size_t i = 0; i < params.size() && err == hipSuccess; ++i)
-    if (params[i].sum_x || params[i].hist) err = rn::launch_stats_zero(params[i], origin);
+    if (!b->plans[i].wave && (params[i].sum_x || params[i].hist))
+      err = rn::launch_stats_zero(params[i], origin);
   if (err == hipSuccess) err = hipEventRecord(b->events[0], origin);
+  std::vector<double> wload(nw, 0.0);
+  for (size_t i : wave_jobs) {
+    if (err != hipSuccess) break;
+    int k = 0;
+    for (int q = 1; q < nw; ++q)
+      if (wload[q] < wload[k]) k = q;
+    hipStream_t st = b->streams[nb + 1 + k];
+    if (wload[k] == 0.0) err = hipStreamWaitEvent(st, b->events[0], 0);
+    wload[k] += b->work[i];
+    if (err == hipSuccess) err = rn_internal::launch_plan(b->plans[i], st);
+  }
+  for (int k = 0; k < nw && err == hipSuccess; ++k) {
+    err = hipEventRecord(b->events[nb + 1 + k], b->streams[nb + 1 + k]);
+    if (err == hipSuccess) err = hipStreamWaitEvent(origin, b->events[nb + 1 + k], 0);
+  }
   for (int g = 0; g < nb && err == hipSuccess; ++g) {
     hipStream_t st = b->streams[g + 1];
     err = hipStreamWaitEvent(st, b->events[0], 0);
@@ -303,7 +331,7 @@ hipError_t capture_persistent(rn_batch* b) {
     if (err == hipSuccess) err = hipStreamWaitEvent(origin, b->events[g + 1], 0);
   }
   for (size_t i = 0; i < params.size() && err == hipSuccess; ++i)
-    if (params[i].sum_x) err = rn::launch_stats_finish(params[i], origin);
+    if (!b->plans[i].wave && params[i].sum_x) err = rn::launch_stats_finish(params[i], origin);
   hipGraph_t gph = nullptr;
   e = hipStreamEndCapture(origin, &gph);
   if (err != hipSuccess) {
@@ -397,6 +425,7 @@ int rn_batch_tune(rn_batch* b, void* hip_stream) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     load_tuned();
     for (size_t i = 0; i < b->plans.size(); ++i) {
+      if (b->plans[i].wave) continue;  // not a work-queue job
       const TuneKey k = tune_key(b->plans[i]);
       if (g_tuned.count(k)) continue;
       auto it = todo.find(k);

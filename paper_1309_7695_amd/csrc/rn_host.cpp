@@ -462,6 +462,21 @@ hipError_t stage_network_now(const rn_network* net) {
   return e;
 }
 
+// The one-wave-per-trajectory kernel, for networks without a compiled kernel:
+// RN_WSWEEP=0 never, =1 whenever the network fits it, else (default) when the
+// sweep has at most kWsweepAutoTraj trajectories per compute unit, i.e. when
+// the lane-per-trajectory kernel would leave most SIMDs idle or give each of
+// its waves a long serial critical path.
+constexpr int64_t kWsweepAutoTraj = 64;
+
+bool use_wsweep(const rn_network* net, int64_t n_traj, int n_cu) {
+  if (!rn::wsweep_fits(net->N, net->dev.M_real)) return false;
+  const char* e = std::getenv("RN_WSWEEP");
+  if (e && e[0] == '0') return false;
+  if (e && e[0] == '1') return true;
+  return n_traj <= kWsweepAutoTraj * n_cu;
+}
+
 int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
                bool wait_compile) {
   if (!net || !a) return RN_E_INVALID_ARG;
@@ -569,6 +584,7 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
     if (plan.lds > (size_t)max_lds) plan.fn = nullptr;
   }
   plan.ssa_dep = plan.fn && ssa_dep;
+  plan.wave = !plan.fn && use_wsweep(net, a->n_traj, n_cu);
   return RN_OK;
 }
 
@@ -600,6 +616,7 @@ hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
     const rn::SweepParams q =
         sub_range(plan.p, off, std::min(kLaunchChunk, plan.p.n_traj - off));
     if (plan.fn) e = rn::jit_launch(plan.fn, q, plan.wg, plan.lds, stream);
+    else if (plan.wave) e = rn::launch_wsweep(q, plan.precision == RN_FP32, stream);
     else if (plan.precision == RN_FP32) e = rn::launch_sweep_f32(q, plan.cfg, stream);
     else e = rn::launch_sweep_f64(q, plan.cfg, stream);
   }
@@ -638,7 +655,8 @@ int rn_sweep_kernel_kind(const rn_network* net, int32_t precision, int64_t n_tra
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return device_error(e);
   const int jwg = n_traj >= (int64_t)256 * n_cu ? 256 : 64;
-  return network_kernel(net, precision, jwg) ? 1 : 0;
+  if (network_kernel(net, precision, jwg)) return 1;
+  return rn_internal::use_wsweep(net, n_traj, n_cu) ? 2 : 0;
 }
 
 void rn_compile_drain(void) { rn::jit_drain(); }

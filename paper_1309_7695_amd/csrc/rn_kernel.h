@@ -177,6 +177,15 @@ hipError_t ode_scratch(double** ptr);
 // Rosenbrock 4(3) rate-equation sweep (rn_ros.hip): one wave per trajectory;
 // ros_fits says whether a network fits it (at most 64 species, W in LDS).
 bool ros_fits(int n_species, int m_real);
+
+// The one-wave-per-trajectory sweep (rn_wsweep.hip): networks of at most
+// kWsweepMaxSpecies species and kWsweepMaxReactions reactions.
+constexpr int kWsweepMaxSpecies = 512, kWsweepMaxReactions = 512;
+bool wsweep_fits(int n_species, int m_real);
+// Dynamic LDS of its 64-lane workgroup.
+size_t wsweep_lds_bytes(int n_species, int m_real, bool fp32);
+// Enqueue it: one workgroup per trajectory of p (p.net.M_real <= 512).
+hipError_t launch_wsweep(const SweepParams& p, bool fp32, hipStream_t stream);
 hipError_t launch_ros(const OdeParams& p, hipStream_t stream);
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,

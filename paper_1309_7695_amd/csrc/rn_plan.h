@@ -16,6 +16,7 @@ struct SweepPlan {
   int wg = 0;                  // workgroup size of the network-compiled kernel
   size_t lds = 0;              // its dynamic LDS bytes
   bool ssa_dep = false;        // it is the dependency-graph exact-SSA kernel
+  bool wave = false;           // the one-wave-per-trajectory kernel (rn_wsweep.hip)
   rn::LaunchCfg cfg{};         // generic kernel configuration
   size_t lane_lds = 0;         // generic kernel LDS bytes per lane
   int max_segs = 0;            // rate register vectors of the generic kernel (0: rates in memory)

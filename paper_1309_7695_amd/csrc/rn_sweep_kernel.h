@@ -116,8 +116,13 @@ __device__ __forceinline__ void sweep_block(const SweepParams& p, int64_t tl0) {
   // c_j of the rates array, for the NSEG == 0 form; the null reactions that
   // pad M to whole rate vectors have no row there and rate 0, as in the
   // register form.
+  // The row index is clamped rather than branched on, so that many of these
+  // loads can be in flight at once.
   const int m_real = g.M_real;
-  auto mrate = [&](int j) -> R { return j < m_real ? (R)crate[(int64_t)j * rld] : R(0); };
+  auto mrate = [&](int j) -> R {
+    const R v = (R)crate[(int64_t)min(j, m_real - 1) * rld];
+    return j < m_real ? v : R(0);
+  };
 
   // Mass-action propensity a_j = c_j * h_j(x), h_j = s_j * (x[ia] * (x[ib] + db)).
   auto prop = [&](int j, R cj) -> R {
@@ -149,7 +154,31 @@ __device__ __forceinline__ void sweep_block(const SweepParams& p, int64_t tl0) {
       f(j0 + 3, q3, q3 * hval<R>(A3, B3 + L3.db, L3.dimer));
     };
     if constexpr (NSEG == 0) {
+      // Rates from memory in chunks of 16: the next chunk's loads are issued
+      // before the current chunk is used, so their latency overlaps the
+      // arithmetic instead of stalling every group of four.
       int j = 0;
+      R q[16], nq[16];
+      if (M >= 16) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) q[e] = mrate(e);
+      }
+      for (; j + 16 <= M; j += 16) {
+        if (j + 32 <= M) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) nq[e] = mrate(j + 16 + e);
+        }
+        group(j, q[0], q[1], q[2], q[3]);
+        if (!more()) return;
+        group(j + 4, q[4], q[5], q[6], q[7]);
+        if (!more()) return;
+        group(j + 8, q[8], q[9], q[10], q[11]);
+        if (!more()) return;
+        group(j + 12, q[12], q[13], q[14], q[15]);
+        if (!more()) return;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) q[e] = nq[e];
+      }
       for (; j + 4 <= M; j += 4) {
         group(j, mrate(j), mrate(j + 1), mrate(j + 2), mrate(j + 3));
         if (!more()) return;
@@ -321,7 +350,30 @@ __device__ __forceinline__ void sweep_block(const SweepParams& p, int64_t tl0) {
         for (int r = 0; r < g.n_rs; ++r) {
           const TauSpecies ts = rs_at(g.rs, r);
           R mu = R(0), sig = R(0);
-          for (int e = ts.begin; e < ts.end; ++e) {
+          // four entries at a time: their table, rate and count loads are all
+          // issued before the first sum; the sums keep the entries' order
+          int e = ts.begin;
+          for (; e + 4 <= ts.end; e += 4) {
+            int2 en[4];
+            R a[4];
+            bool skip[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) en[u] = cld2(g.rs_ent, e + u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = rate_at(en[u].x);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              skip[u] = critbit(en[u].x);
+              a[u] = prop(en[u].x, a[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (skip[u]) continue;
+              mu = mu + (R)en[u].y * a[u];
+              sig = sig + (R)(en[u].y * en[u].y) * a[u];
+            }
+          }
+          for (; e < ts.end; ++e) {
             const int2 en = cld2(g.rs_ent, e);
             if (critbit(en.x)) continue;
             const R a = prop(en.x, rate_at(en.x));
@@ -441,10 +493,13 @@ __device__ __forceinline__ void sweep_block(const SweepParams& p, int64_t tl0) {
         } else {
           for (int base = 0; base < M; base += 16) {
             V16 lam;
+            R q[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) q[e] = mrate(base + e);  // 0 past the last row
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
               const int j = base + e;
-              lam[e] = (j < M && !critbit(j)) ? prop(j, mrate(j)) * taur : R(0);
+              lam[e] = (j < M && !critbit(j)) ? prop(j, q[e]) * taur : R(0);
             }
             draw_block(base, lam);
           }

@@ -425,13 +425,15 @@ class Batch:
 
 def sweep_kernel_kind(net: Network, n_traj, precision="fp64"):
     """``rn_sweep_kernel_kind``: "network" when rn_sweep runs a kernel compiled
-    for this network (compiling it now if needed), "generic" otherwise."""
+    for this network (compiling it now if needed), "wave" for the generic
+    one-wave-per-trajectory kernel, "generic" for the generic
+    one-lane-per-trajectory kernel."""
     if precision not in PRECISIONS:
         raise ValueError("precision must be 'fp64' or 'fp32'")
     rc = lib().rn_sweep_kernel_kind(net.handle, PRECISIONS[precision], int(n_traj))
     if rc < 0:
         raise RNError(rc, "rn_sweep_kernel_kind")
-    return "network" if rc == 1 else "generic"
+    return {1: "network", 2: "wave"}.get(rc, "generic")
 
 
 class Server:

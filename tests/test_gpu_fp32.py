@@ -139,7 +139,7 @@ def test_fp32_stiff_full_launch_vs_oracle():
     # rate constants (independent seeds), by the per-cell rule above.
     w = gen.stiff_workload()
     assert w.n_traj == 65536
-    assert rn.sweep_kernel_kind(rn.Network(w.net), w.n_traj, "fp32") in ("network", "generic")
+    assert rn.sweep_kernel_kind(rn.Network(w.net), w.n_traj, "fp32") in ("network", "generic", "wave")
     _say(f"case fp32 stiff full launch: T={w.n_traj}")
     out, st = rn.run(w.net, w.rates, w.x0, w.times, seed=109, precision="fp32")
     assert out.min() >= 0

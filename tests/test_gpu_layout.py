@@ -55,7 +55,8 @@ def test_traj_major_full_workgroups():
     _both(w, 6)
 
 
-def test_traj_major_generic_kernel():
+def test_traj_major_generic_kernel(monkeypatch):
+    monkeypatch.setenv("RN_WSWEEP", "0")
     w = gen.synthetic_workload(n_traj=257, n_species=70, n_reactions=140, t_end=1.0,
                                n_samples=6, seed=3)
     assert rn.sweep_kernel_kind(rn.Network(w.net), w.n_traj) == "generic"

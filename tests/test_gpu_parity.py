@@ -112,8 +112,11 @@ def test_stiff_network_subset():
     _compare(out, st, ref, rst, "stiff 30x80, 200 trajectories")
 
 
-def test_large_network():
-    # 500 reactions, 250 species: the largest network of the uneven batch
+@pytest.mark.parametrize("form", ["0", "1"])
+def test_large_network(monkeypatch, form):
+    # 500 reactions, 250 species: the largest network of the uneven batch, on
+    # the lane-per-trajectory (RN_WSWEEP=0) and the wave-per-trajectory form
+    monkeypatch.setenv("RN_WSWEEP", form)
     net = gen.random_network(3001, 250, 500)
     rng = np.random.default_rng(5)
     T = 96
@@ -241,6 +244,7 @@ def test_network_compiled_kernel_matches_generic(monkeypatch, precision):
     assert rn.sweep_kernel_kind(net, w.n_traj, precision) == "network"
     a, sa = rn.run(net, w.rates, w.x0, w.times, seed=21, precision=precision)
     monkeypatch.setenv("RN_JIT", "0")
+    monkeypatch.setenv("RN_WSWEEP", "0")
     assert rn.sweep_kernel_kind(net, w.n_traj, precision) == "generic"
     b, sb = rn.run(net, w.rates, w.x0, w.times, seed=21, precision=precision)
     same = np.all(a == b, axis=(0, 1)) & np.all(sa == sb, axis=1)
@@ -248,6 +252,10 @@ def test_network_compiled_kernel_matches_generic(monkeypatch, precision):
     assert same.all()
 
 
-def test_large_network_uses_generic_kernel():
+def test_large_network_uses_generic_kernel(monkeypatch):
+    # no compiled kernel; few trajectories: one wave each, unless RN_WSWEEP=0
     net = rn.Network(gen.random_network(3001, 250, 500))
+    monkeypatch.delenv("RN_WSWEEP", raising=False)
+    assert rn.sweep_kernel_kind(net, 96) == "wave"
+    monkeypatch.setenv("RN_WSWEEP", "0")
     assert rn.sweep_kernel_kind(net, 96) == "generic"

@@ -109,8 +109,9 @@ def test_stats_stiff_subset():
     _case(gen.stiff_workload(n_traj=200), 4, bins=8)
 
 
-def test_stats_generic_kernel_network():
+def test_stats_generic_kernel_network(monkeypatch):
     # 70 species: the generic kernel records from its LDS counts
+    monkeypatch.setenv("RN_WSWEEP", "0")
     w = gen.synthetic_workload(n_traj=257, n_species=70, n_reactions=140, t_end=2.0,
                                n_samples=9, seed=3)
     assert rn.sweep_kernel_kind(rn.Network(w.net), w.n_traj) == "generic"

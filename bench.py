@@ -767,7 +767,8 @@ def batch_main(args, torch, gen, rn):
     setup_s = time.perf_counter() - t0
     kind_list = [kinds[(k, args.precision)] for k in range(len(jobs))]
     print(f"[bench] batch of {len(jobs)}: {kind_list.count('network')} network-compiled, "
-          f"{kind_list.count('generic')} generic kernels; setup {setup_s:.1f} s",
+          f"{kind_list.count('wave')} wave-per-trajectory, {kind_list.count('generic')} "
+          f"lane generic kernels; setup {setup_s:.1f} s",
           file=sys.stderr, flush=True)
     kw = dict(precision=args.precision)
 
@@ -863,8 +864,7 @@ def batch_main(args, torch, gen, rn):
                    "n_traj_total": int(sum(j["T"] for j in jobs)),
                    "reactions": [int(j["net"].n_reactions) for j in jobs],
                    "steps_per_batch": steps},
-        "kernels": {"network": kind_list.count("network"),
-                    "generic": kind_list.count("generic")},
+        "kernels": {k: kind_list.count(k) for k in ("network", "wave", "generic")},
         "setup_s": {"kernel_compile": setup_s},
         "forms": results,
         "one_at_a_time": ({"precision": seq_prec, "value": seq_steps / seq_s,

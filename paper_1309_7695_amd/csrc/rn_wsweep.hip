@@ -59,18 +59,31 @@ __device__ __forceinline__ R wave_min(R v) {
 }
 
 // Index-order walk: sum = ((v_0 + v_1) + v_2) + ... over reactions j < m, where
-// v_j sits on lane j % 64 in v[j / 64]; lane l gets in pre[k] the partial sum
-// through reaction 64k + l.  Every lane returns the full sum.
-template <int K, typename S>
+// v_j sits on lane j % 64 in v[j / 64].  With kPre, lane l also gets in pre[k]
+// the partial sum through reaction 64k + l.  Every lane returns the full sum.
+// Eight broadcasts are issued ahead of their adds, so that only the chain of
+// additions is serial.
+template <int K, bool kPre, typename S>
 __device__ __forceinline__ S ordered_sum(const S (&v)[K], S (&pre)[K], int m, int lane) {
   S sum = S(0);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    pre[k] = S(0);
+    if constexpr (kPre) pre[k] = S(0);
     const int n = min(64, m - 64 * k);
-    for (int l = 0; l < n; ++l) {
+    int l = 0;
+    for (; l + 8 <= n; l += 8) {
+      S b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = bcast(v[k], l + u);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sum = sum + b[u];
+        if constexpr (kPre) pre[k] = lane == l + u ? sum : pre[k];
+      }
+    }
+    for (; l < n; ++l) {
       sum = sum + bcast(v[k], l);
-      pre[k] = lane == l ? sum : pre[k];
+      if constexpr (kPre) pre[k] = lane == l ? sum : pre[k];
     }
   }
   return sum;
@@ -217,7 +230,7 @@ __global__ __launch_bounds__(64) void wsweep_kernel(const SweepParams p) {
 #pragma unroll
       for (int k = 0; k < K; ++k) a[k] = prop(k);
       R pre[K];
-      const R sum = ordered_sum<K, R>(a, pre, M, lane);
+      const R sum = ordered_sum<K, true, R>(a, pre, M, lane);
       if (sum == R(0)) {
         finish(kStAbsorbed);
         break;
@@ -294,8 +307,8 @@ __global__ __launch_bounds__(64) void wsweep_kernel(const SweepParams p) {
           }
         }
       }
-      double pre[K];
-      const double sum = ordered_sum<K, double>(ad, pre, M, lane);
+      double unused[K];
+      const double sum = ordered_sum<K, false, double>(ad, unused, M, lane);
       // critical bits as words of 32 reactions
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -350,15 +363,22 @@ __global__ __launch_bounds__(64) void wsweep_kernel(const SweepParams p) {
     }
     bool crk[K];
     double vc[K];
+    uint64_t cmask[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int j = lane + 64 * k;
       a[k] = prop(k);
       crk[k] = j < M && ((critw[j >> 5] >> (j & 31)) & 1u);
-      vc[k] = crk[k] ? (double)a[k] : 0.0;
+      vc[k] = (double)a[k];
+      cmask[k] = __ballot(crk[k]);
     }
-    double prc[K];
-    const double a0c = ordered_sum<K, double>(vc, prc, M, lane);
+    // a0c: the critical reactions' propensities added in index order (the
+    // others contribute nothing), one broadcast per critical reaction
+    double a0c = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      for (uint64_t b = cmask[k]; b; b &= b - 1) a0c = a0c + bcast(vc[k], __builtin_ctzll(b));
+    }
     Words ev = {0u, 0u, 0u, 0u};
     double tau_c = __builtin_inf();
     if (a0c > 0.0) {
@@ -385,15 +405,22 @@ __global__ __launch_bounds__(64) void wsweep_kernel(const SweepParams p) {
                          p.cle_threshold);
     }
     if (fire) {
+      // the first critical reaction whose running sum exceeds r, walking the
+      // same additions again; else the last one with a positive propensity
       const double r = u53(ev.w2, ev.w3) * a0c;
-      bool hit[K], pos[K];
+      int jc = -1, last = -1;
+      double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        hit[k] = crk[k] && r < prc[k];
-        pos[k] = crk[k] && vc[k] > 0.0;
+        for (uint64_t b = cmask[k]; b && jc < 0; b &= b - 1) {
+          const int l = __builtin_ctzll(b);
+          const double av = bcast(vc[k], l);
+          acc = acc + av;
+          if (av > 0.0) last = 64 * k + l;
+          if (r < acc) jc = 64 * k + l;
+        }
       }
-      int jc = first_set<K>(hit);
-      if (jc < 0) jc = last_set<K>(pos);
+      if (jc < 0) jc = last;
       if (jc < 0) {
         finish(kStAbsorbed);
         break;

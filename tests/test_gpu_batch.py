@@ -273,3 +273,22 @@ def test_persistent_rates_from_memory_on_padded_networks(tmp_path):
     _say(r.stdout + r.stderr[-1500:])
     assert r.returncode == 0
     assert "identical fp64" in r.stdout and "identical fp32" in r.stdout
+
+
+def test_default_kernel_choice_in_both_batch_forms(monkeypatch):
+    # with the default choice, small jobs run one wave per trajectory: the graph
+    # and the persistent form (which puts those jobs on their own branches)
+    # still give every job exactly rn_sweep's results
+    jobs = _jobs()  # (built with the lane kernels pinned)
+    monkeypatch.delenv("RN_WSWEEP", raising=False)
+    kinds = [rn.sweep_kernel_kind(j["net"], j["w"].n_traj) for j in jobs]
+    _say(f"default kernel choice: {kinds}")
+    assert "wave" in kinds
+    ref = _reference(jobs)
+    for persistent in (False, True):
+        b = rn.Batch(persistent=persistent)
+        for j in jobs:
+            b.add(j["net"], j["rates"], j["x0"], j["times"], j["out"], j["stats"],
+                  seed=j["seed"])
+        _batch_matches(jobs, ref, b, f"default choice, persistent={persistent}")
+        b.close()

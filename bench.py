@@ -210,6 +210,12 @@ def serve_main(args, torch, gen, rn):
     tot = sum(steps[k] for k in meas)
     offered = args.serve_rate
     achieved = len(meas) / span
+    # steady state: jobs completed while arrivals were still coming in, over
+    # that window (the span above also holds the drain of the last, heaviest jobs)
+    last_arrival = float(arrivals[len(ws) - 1])
+    first = float(arrivals[meas[0]])
+    in_window = sum(1 for k in meas if done_at[k] <= last_arrival)
+    window_rate = in_window / max(last_arrival - first, 1e-9)
     result = {
         "metric": "serving: trajectory-steps/sec and p50/p99 sweep-job latency (1 GPU)",
         "value": tot / span, "unit": "trajectory-steps/s", "n_gpus": 1,
@@ -222,7 +228,9 @@ def serve_main(args, torch, gen, rn):
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3,
                        "p99": float(np.percentile(lat, 99)) * 1e3},
-        "jobs_per_s": {"offered": offered, "completed": achieved},
+        "jobs_per_s": {"offered": offered, "completed": achieved,
+                       "completed_while_arriving": window_rate},
+        "drain_s": max(done_at[k] for k in meas) - last_arrival,
         "overloaded": bool(achieved < 0.95 * offered),
         "host_s": host,
     }

@@ -225,13 +225,13 @@ int rn_sweep(const rn_network *net, const rn_sweep_args *args, void *hip_stream)
  * rate constants and tables are compile-time values in registers, and it gives
  * the same results as the generic kernels, which run otherwise (also when the
  * environment sets RN_JIT=0 or the compilation fails).  The first rn_sweep of a
- * network and precision pays the compilation on the calling thread.  Sweeps
- * of few trajectories on networks of at most 512 species and 512 reactions run
- * instead one wave per trajectory (lanes over reactions and species): at most
- * 16 trajectories per compute unit for networks that have a compiled kernel,
- * 64 for the others.  The remaining sweeps run one lane per trajectory.
- * RN_WSWEEP=1 picks the wave form whenever the network fits it, RN_WSWEEP=0
- * never.  All kernels give the same trajectories.
+ * network and precision pays the compilation on the calling thread.  The
+ * other networks of at most 512 species and 512 reactions run one wave per
+ * trajectory (lanes over reactions and species), and so do sweeps of at most
+ * 16 trajectories per compute unit on networks with a compiled kernel; the
+ * remaining sweeps run one lane per trajectory.  RN_WSWEEP=1 picks the wave
+ * form whenever the network fits it, RN_WSWEEP=0 never.  All kernels give the
+ * same trajectories.
  * Returns 1 (network-compiled; compiling it now if needed), 0 (generic, one
  * lane per trajectory), 2 (generic, one wave per trajectory), or
  * RN_E_INVALID_ARG / RN_E_DEVICE.

@@ -463,21 +463,22 @@ hipError_t stage_network_now(const rn_network* net) {
 }
 
 // The one-wave-per-trajectory kernel: RN_WSWEEP=0 never, =1 whenever the
-// network fits it; by default, when the sweep has at most kWsweepAutoTraj
-// trajectories per compute unit (kWsweepAutoTrajJit for a network that has a
-// compiled kernel, whose lanes step faster), i.e. when one lane per trajectory
-// would leave most SIMDs idle and give each wave a long serial critical path.
-// Measured on MI355X: for networks of 50-120 reactions the wave form wins up
-// to 15-20 trajectories per CU; for 250-450 reactions without a compiled
-// kernel it wins 2.4x at 57 per CU.
+// network fits it.  By default (measured on MI355X):
+//  * networks too large for a compiled kernel: always (1.3-3x faster than one
+//    lane per trajectory on 170-450 reactions, from 300 to 64k trajectories);
+//  * networks with a compiled kernel: sweeps of at most kWsweepAutoTrajJit
+//    trajectories per CU (the wave form wins there for 50-120 reactions); at
+//    most kWsweepAutoTraj while the compiled kernel is not available yet.
 constexpr int64_t kWsweepAutoTraj = 64, kWsweepAutoTrajJit = 16;
+enum : int { kNoJit = 0, kJitReady = 1, kJitPending = 2 };
 
-bool use_wsweep(const rn_network* net, int64_t n_traj, int n_cu, bool compiled) {
+bool use_wsweep(const rn_network* net, int64_t n_traj, int n_cu, int jit) {
   if (!rn::wsweep_fits(net->N, net->dev.M_real)) return false;
   const char* e = std::getenv("RN_WSWEEP");
   if (e && e[0] == '0') return false;
   if (e && e[0] == '1') return true;
-  return n_traj <= (compiled ? kWsweepAutoTrajJit : kWsweepAutoTraj) * n_cu;
+  if (jit == kNoJit) return true;
+  return n_traj <= (jit == kJitReady ? kWsweepAutoTrajJit : kWsweepAutoTraj) * n_cu;
 }
 
 // Whether the network has (or can compile) a network-compiled kernel.
@@ -585,7 +586,8 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   const char* sk = std::getenv("RN_SSA_KERNEL");
   const bool ssa_dep = a->method == RN_METHOD_SSA && sk && std::strcmp(sk, "dep") == 0 &&
                        net->M * (fp32 ? 1 : 2) <= rn::kJitSsaDepMaxWords;
-  plan.wave = !ssa_dep && use_wsweep(net, a->n_traj, n_cu, has_network_kernel(net));
+  plan.wave = !ssa_dep &&
+              use_wsweep(net, a->n_traj, n_cu, has_network_kernel(net) ? kJitReady : kNoJit);
   if (!plan.wave) plan.fn = network_kernel(net, a->precision, plan.wg, wait_compile, ssa_dep);
   if (plan.fn) {
     plan.lds = ssa_dep ? rn::jit_ssa_lds_bytes(net->N, net->M, net->nnz, plan.wg, fp32)
@@ -595,7 +597,8 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   plan.ssa_dep = plan.fn && ssa_dep;
   // a network whose compiled kernel is missing (compile failed or still in
   // flight) takes the generic kernels' rule
-  if (!plan.fn && !plan.wave && !ssa_dep) plan.wave = use_wsweep(net, a->n_traj, n_cu, false);
+  if (!plan.fn && !plan.wave && !ssa_dep)
+    plan.wave = use_wsweep(net, a->n_traj, n_cu, has_network_kernel(net) ? kJitPending : kNoJit);
   return RN_OK;
 }
 
@@ -666,9 +669,13 @@ int rn_sweep_kernel_kind(const rn_network* net, int32_t precision, int64_t n_tra
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return device_error(e);
   const int jwg = n_traj >= (int64_t)256 * n_cu ? 256 : 64;
-  if (rn_internal::use_wsweep(net, n_traj, n_cu, rn_internal::has_network_kernel(net))) return 2;
+  const bool jit = rn_internal::has_network_kernel(net);
+  if (rn_internal::use_wsweep(net, n_traj, n_cu,
+                              jit ? rn_internal::kJitReady : rn_internal::kNoJit))
+    return 2;
   if (network_kernel(net, precision, jwg)) return 1;
-  return rn_internal::use_wsweep(net, n_traj, n_cu, false) ? 2 : 0;
+  return rn_internal::use_wsweep(net, n_traj, n_cu,
+                                 jit ? rn_internal::kJitPending : rn_internal::kNoJit) ? 2 : 0;
 }
 
 void rn_compile_drain(void) { rn::jit_drain(); }

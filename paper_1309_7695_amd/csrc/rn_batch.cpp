@@ -4,9 +4,8 @@
 // The jobs are independent (paper, Aims and motivation section: sweeps repeat
 // many simulations), so the graph runs them as parallel branches: the first
 // launch forks from an internal origin stream onto a small pool of branch
-// streams, enqueues each job's kernel on one branch (largest jobs first by
-// trajectories x reactions, each to the least-loaded branch), joins, and
-// captures the whole pattern; every
+// streams, enqueues each job's kernel on one branch (largest jobs first, each
+// to the least-loaded branch), joins, and captures the whole pattern; every
 // later launch replays it with a single hipGraphLaunch on the caller's stream.
 // Small jobs then fill the compute units that large ones leave idle, and the
 // host cost of a batch is one launch.  The graph holds kernel nodes only.
@@ -168,23 +167,18 @@ hipError_t capture(rn_batch* b) {
   hipError_t err = hipEventRecord(b->events[0], origin);
   for (int k = 1; k <= nb && err == hipSuccess; ++k)
     err = hipStreamWaitEvent(b->streams[k], b->events[0], 0);
-  // largest jobs first (trajectories x reactions), each onto the least-loaded
-  // branch, so the longest job starts at once
+  // largest jobs first, each onto the least-loaded branch
   std::vector<size_t> order(b->plans.size());
-  std::vector<double> cost(b->plans.size());
-  for (size_t i = 0; i < order.size(); ++i) {
-    order[i] = i;
-    cost[i] = b->work[i] * b->plans[i].n_reactions;
-  }
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
-                   [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+                   [&](size_t x, size_t y) { return b->work[x] > b->work[y]; });
   std::vector<double> load(nb + 1, 0.0);
   for (size_t i : order) {
     if (err != hipSuccess) break;
     int k = 1;
     for (int q = 2; q <= nb; ++q)
       if (load[q] < load[k]) k = q;
-    load[k] += cost[i];
+    load[k] += b->work[i];
     err = rn_internal::launch_plan(b->plans[i], b->streams[k]);
   }
   for (int k = 1; k <= nb && err == hipSuccess; ++k) {

@@ -544,6 +544,7 @@ int plan_sweep(const rn_network* net, const rn_sweep_args* a, SweepPlan& plan,
   plan.max_segs = cfg.rate_segs;
   plan.n_species = net->N;
   plan.n_reactions = net->M;
+  plan.n_simd = 4 * n_cu;
   plan.nnz = net->nnz;
 
   plan.net = net;
@@ -630,7 +631,7 @@ hipError_t launch_plan(const SweepPlan& plan, hipStream_t stream) {
     const rn::SweepParams q =
         sub_range(plan.p, off, std::min(kLaunchChunk, plan.p.n_traj - off));
     if (plan.fn) e = rn::jit_launch(plan.fn, q, plan.wg, plan.lds, stream);
-    else if (plan.wave) e = rn::launch_wsweep(q, plan.precision == RN_FP32, stream);
+    else if (plan.wave) e = rn::launch_wsweep(q, plan.precision == RN_FP32, plan.n_simd, stream);
     else if (plan.precision == RN_FP32) e = rn::launch_sweep_f32(q, plan.cfg, stream);
     else e = rn::launch_sweep_f64(q, plan.cfg, stream);
   }

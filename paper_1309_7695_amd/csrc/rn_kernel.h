@@ -184,8 +184,9 @@ constexpr int kWsweepMaxSpecies = 512, kWsweepMaxReactions = 512;
 bool wsweep_fits(int n_species, int m_real);
 // Dynamic LDS of its 64-lane workgroup.
 size_t wsweep_lds_bytes(int n_species, int m_real, bool fp32);
-// Enqueue it: one workgroup per trajectory of p (p.net.M_real <= 512).
-hipError_t launch_wsweep(const SweepParams& p, bool fp32, hipStream_t stream);
+// Enqueue it: one workgroup per trajectory of p (p.net.M_real <= 512); n_simd:
+// the device's SIMDs (4 per CU), which picks the occupancy of the largest form.
+hipError_t launch_wsweep(const SweepParams& p, bool fp32, int n_simd, hipStream_t stream);
 hipError_t launch_ros(const OdeParams& p, hipStream_t stream);
 hipError_t launch_hybrid(const HybridParams& p, hipStream_t stream);
 hipError_t launch_moments(const int32_t* out, int64_t out_ld, int64_t rows, int64_t n_traj,

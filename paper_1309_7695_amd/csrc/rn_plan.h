@@ -17,6 +17,7 @@ struct SweepPlan {
   size_t lds = 0;              // its dynamic LDS bytes
   bool ssa_dep = false;        // it is the dependency-graph exact-SSA kernel
   bool wave = false;           // the one-wave-per-trajectory kernel (rn_wsweep.hip)
+  int n_simd = 0;              // the device's SIMDs (4 per compute unit)
   rn::LaunchCfg cfg{};         // generic kernel configuration
   size_t lane_lds = 0;         // generic kernel LDS bytes per lane
   int max_segs = 0;            // rate register vectors of the generic kernel (0: rates in memory)

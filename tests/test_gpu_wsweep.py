@@ -160,3 +160,22 @@ def test_wave_kernel_layout_range_and_statistics(generic, monkeypatch):
     got2 = [int(u) + (int(v) << 64) for u, v in zip(q[..., 0].ravel(), q[..., 1].ravel())]
     assert got2 == [int(v) for v in (ref * ref).sum(axis=2).ravel()]
     _say("wave layout, range and statistics: identical")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wave_kernel_two_waves_per_simd(generic, precision):
+    # more trajectories than the chip has SIMDs: the largest form (K = 8) runs
+    # at two waves per SIMD, with registers spilled; still the same trajectories
+    net = gen.random_network(3001, 250, 500)
+    rng = np.random.default_rng(8)
+    T = 1100
+    rates = gen.log_uniform(rng, 1e-4, 1.0, 500)[:, None] * gen.log_uniform(rng, 0.1, 10, (500, T))
+    w = gen.Workload("random 250x500", net, np.ascontiguousarray(rates),
+                     rng.integers(0, 1001, size=250).astype(np.int32), gen.sample_times(0.5, 3))
+    out, st = _vs_lanes(generic, w, 38, f"wave two waves per SIMD {precision}",
+                        precision=precision)
+    if precision == "fp64":
+        for t in np.linspace(0, T - 1, 6).astype(int):
+            ref, rst, _ = oracle.run(w.net, w.rates, w.x0, w.times, seed=38,
+                                     traj_range=(int(t), int(t) + 1))
+            assert np.array_equal(out[:, :, t], ref[:, :, 0]) and np.array_equal(st[t], rst[0])

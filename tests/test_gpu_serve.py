@@ -33,8 +33,13 @@ def _job_bytes(w):
     return r(M * T * 8) + r(N * 4) + r(S * 8) + r(S * N * T * 4) + r(T * 32)
 
 
+@pytest.mark.parametrize("choice", ["lanes", "default"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_server_mix_equals_alone(precision):
+def test_server_mix_equals_alone(precision, choice, monkeypatch):
+    # "default": the library's kernel choice, which runs these small jobs one
+    # wave per trajectory (the reference sweeps below then run the same way)
+    if choice == "default":
+        monkeypatch.delenv("RN_WSWEEP", raising=False)
     arrivals, ws = gen.serve_jobs(n_jobs=8, seed=5100, t_scale=0.02, t_end_scale=0.02,
                                   n_samples=11)
     budget = int(1.5 * max(_job_bytes(w) for w in ws))  # forces queueing

@@ -494,28 +494,33 @@ void wsweep_kernel(const SweepParams p) {
   }
 }
 
-// K = 8 needs 275-302 registers, one wave per SIMD.  The two-wave form caps it
-// at 256 (16-53 registers spill to scratch): 1.5-1.65x faster on sweeps of
-// 1,900-15,000 trajectories of 300-450 reactions, 6% slower on 285 trajectories,
-// where the chip has SIMDs to spare anyway.
+// Occupancy forms, for sweeps with more trajectories than the chip has SIMDs:
+//  * K = 8 needs 275-302 registers, one wave per SIMD; the two-wave form caps it
+//    at 256 (16-53 registers spill to scratch) and is 1.5-1.65x faster on
+//    sweeps of 1,900-15,000 trajectories of 300-450 reactions (6% slower on
+//    285 trajectories, where the chip has SIMDs to spare anyway);
+//  * K = 1 runs three waves per SIMD (167-168 registers, at most 15 spilled):
+//    1.12-1.45x on 2,100-3,100 trajectories of 20-55 reactions.  For K = 2 and
+//    4 three waves measured no faster, or slower.
 template <int K, typename R>
-hipError_t launch_k(const SweepParams& p, size_t lds, bool two_waves, hipStream_t stream) {
-  if (K == 8 && two_waves)
-    hipLaunchKernelGGL((wsweep_kernel<K, R, 2>), dim3((unsigned)p.n_traj), dim3(64), lds, stream,
-                       p);
+hipError_t launch_k(const SweepParams& p, size_t lds, bool many, hipStream_t stream) {
+  const dim3 grid((unsigned)p.n_traj), block(64);
+  if (K == 8 && many)
+    hipLaunchKernelGGL((wsweep_kernel<K, R, 2>), grid, block, lds, stream, p);
+  else if (K == 1 && many)
+    hipLaunchKernelGGL((wsweep_kernel<K, R, 3>), grid, block, lds, stream, p);
   else
-    hipLaunchKernelGGL((wsweep_kernel<K, R, 1>), dim3((unsigned)p.n_traj), dim3(64), lds, stream,
-                       p);
+    hipLaunchKernelGGL((wsweep_kernel<K, R, 1>), grid, block, lds, stream, p);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_prec(const SweepParams& p, size_t lds, bool two_waves, hipStream_t stream) {
+hipError_t launch_prec(const SweepParams& p, size_t lds, bool many, hipStream_t stream) {
   const int m = p.net.M_real;
-  if (m <= 64) return launch_k<1, R>(p, lds, two_waves, stream);
-  if (m <= 128) return launch_k<2, R>(p, lds, two_waves, stream);
-  if (m <= 256) return launch_k<4, R>(p, lds, two_waves, stream);
-  if (m <= 512) return launch_k<8, R>(p, lds, two_waves, stream);
+  if (m <= 64) return launch_k<1, R>(p, lds, many, stream);
+  if (m <= 128) return launch_k<2, R>(p, lds, many, stream);
+  if (m <= 256) return launch_k<4, R>(p, lds, many, stream);
+  if (m <= 512) return launch_k<8, R>(p, lds, many, stream);
   return hipErrorInvalidValue;
 }
 
@@ -534,8 +539,8 @@ size_t wsweep_lds_bytes(int n_species, int m_real, bool fp32) {
 hipError_t launch_wsweep(const SweepParams& p, bool fp32, int n_simd, hipStream_t stream) {
   if (p.n_traj <= 0) return hipSuccess;
   const size_t lds = wsweep_lds_bytes(p.net.N, p.net.M_real, fp32);
-  const bool two = p.n_traj > (int64_t)n_simd;
-  return fp32 ? launch_prec<float>(p, lds, two, stream) : launch_prec<double>(p, lds, two, stream);
+  const bool many = p.n_traj > (int64_t)n_simd;
+  return fp32 ? launch_prec<float>(p, lds, many, stream) : launch_prec<double>(p, lds, many, stream);
 }
 
 }  // namespace rn

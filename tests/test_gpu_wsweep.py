@@ -179,3 +179,14 @@ def test_wave_kernel_two_waves_per_simd(generic, precision):
             ref, rst, _ = oracle.run(w.net, w.rates, w.x0, w.times, seed=38,
                                      traj_range=(int(t), int(t) + 1))
             assert np.array_equal(out[:, :, t], ref[:, :, 0]) and np.array_equal(st[t], rst[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wave_kernel_three_waves_per_simd(generic, precision):
+    # the smallest form (K = 1) runs three waves per SIMD once the sweep
+    # outnumbers the SIMDs; the 3-reaction enzyme network, 2,500 trajectories
+    w = gen.enzyme_workload(n_traj=2500)
+    out, st = _vs_lanes(generic, w, 39, f"wave three waves per SIMD {precision}",
+                        precision=precision)
+    if precision == "fp64":
+        _vs_oracle(out, st, w, 39, "wave three waves per SIMD")

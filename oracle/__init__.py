@@ -75,6 +75,10 @@ def lib():
         L.orc_cle_many.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_int32, C.c_int64,
                                    C.c_void_p]
         L.orc_cle_many.restype = None
+        L.orc_pick_index.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p]
+        L.orc_pick_index.restype = C.c_int
+        L.orc_critical_fires.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_critical_fires.restype = C.c_int
         L.orc_run.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_void_p]
@@ -111,6 +115,19 @@ def poisson_many(lam, seed, n, j=0, n0=0):
     out = np.zeros(int(n), dtype=np.int64)
     lib().orc_poisson_many(float(lam), int(seed), int(n0), int(j), int(n), out.ctypes.data)
     return out
+
+
+def pick_index(a, r, allowed=None):
+    """The direct method's selection over the propensities ``a`` for ``r``."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    al = None if allowed is None else np.ascontiguousarray(allowed, dtype=np.int32)
+    return int(lib().orc_pick_index(a.ctypes.data, len(a), float(r),
+                                    None if al is None else al.ctypes.data))
+
+
+def critical_fires(tau_c, tau_p, delta):
+    """1 when the critical race is won (see ``orc_critical_fires``)."""
+    return int(lib().orc_critical_fires(float(tau_c), float(tau_p), float(delta)))
 
 
 def _desc(net):

@@ -267,19 +267,40 @@ static double all_propensities(traj_state *T) {
 
 static uint64_t steps_taken(const traj_state *T) { return T->leaps + T->ssa + T->rej; }
 
-/* First j (index order, among the allowed ones) whose running sum of a_j exceeds
- * r; when rounding leaves none, the last allowed j with a_j > 0. */
-static int pick_reaction(traj_state *T, double r, const int *allowed) {
+/* The direct method's selection (Gillespie 1977): the first j, in index order
+ * among the allowed ones, whose running sum a_0 + ... + a_j exceeds r; when
+ * rounding leaves none, the last allowed j with a_j > 0.  *terms counts the
+ * terms added. */
+static int pick_index(const double *a, int m, double r, const int *allowed, uint64_t *terms) {
   double acc = 0.0;
   int last = -1;
-  for (int j = 0; j < T->g->M; ++j) {
+  for (int j = 0; j < m; ++j) {
     if (allowed && !allowed[j]) continue;
-    if (T->ops) T->ops->select_terms++;
-    acc = acc + T->a[j];
-    if (T->a[j] > 0.0) last = j;
+    if (terms) ++*terms;
+    acc = acc + a[j];
+    if (a[j] > 0.0) last = j;
     if (r < acc) return j;
   }
   return last;
+}
+
+static int pick_reaction(traj_state *T, double r, const int *allowed) {
+  return pick_index(T->a, T->g->M, r, allowed, T->ops ? &T->ops->select_terms : NULL);
+}
+
+/* The critical race of Cao, Gillespie and Petzold (2006): a critical reaction
+ * fires when its waiting time tau'' is no longer than the leap bound tau'; here
+ * also no later than the next sample time (delta away). */
+static int critical_fires(double tau_c, double tau_p, double delta) {
+  return (tau_c <= tau_p) && (tau_c <= delta);
+}
+
+int orc_pick_index(const double *a, int m, double r, const int *allowed) {
+  return pick_index(a, m, r, allowed, NULL);
+}
+
+int orc_critical_fires(double tau_c, double tau_p, double delta) {
+  return critical_fires(tau_c, tau_p, delta);
 }
 
 /* Result codes of the exact-event loop. */
@@ -399,7 +420,7 @@ static void simulate(traj_state *T) {
         tau_c = -log(1.0 - orc_u53(ev[0], ev[1])) / a0c;
       }
       double delta = T->times[T->s] - T->t;
-      int fire = (tau_c <= tau_p) && (tau_c <= delta);
+      int fire = critical_fires(tau_c, tau_p, delta);
       double tau = fire ? tau_c : (tau_p < delta ? tau_p : delta);
 
       /* Poisson firings of every non-critical reaction over tau; one firing of

@@ -72,6 +72,12 @@ void orc_cle_many(double lam, uint64_t seed, uint32_t n0, int32_t j, int64_t n, 
 /* n variates for trajectory ids 0..n-1 (test helper). */
 void orc_poisson_many(double lam, uint64_t seed, uint32_t n0, int32_t j, int64_t n, int64_t *out);
 
+/* Test hooks for the two decisions whose ties no trajectory statistic can see:
+ * the direct method's selection over propensities a[0..m) (allowed may be
+ * NULL), and the critical race (1 when a critical reaction fires). */
+int orc_pick_index(const double *a, int m, double r, const int *allowed);
+int orc_critical_fires(double tau_c, double tau_p, double delta);
+
 /* Status bits of a trajectory. */
 #define ORC_ST_ABSORBED 1u
 #define ORC_ST_MAXSTEPS 2u

@@ -646,6 +646,9 @@ void prefetch_kernel(const rn_network* net, int32_t precision, int64_t n_traj) {
   if (hipGetDevice(&dev) != hipSuccess || dev != net->device) return;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return;
+  // a sweep that runs one wave per trajectory even once the kernel exists
+  // leaves the compile workers to jobs that need them
+  if (use_wsweep(net, n_traj, n_cu, has_network_kernel(net) ? kJitReady : kNoJit)) return;
   (void)network_kernel(net, precision, n_traj >= (int64_t)256 * n_cu ? 256 : 64, false);
 }
 

@@ -39,7 +39,8 @@ hipError_t stage_network_now(const rn_network* net);
 // RN_OK for hipSuccess, else RN_E_DEVICE (recording the HIP code).
 int device_status(hipError_t e);
 // Start compiling the network's kernel in the background if it is not cached
-// (the launch shape follows n_traj as in plan_sweep).
+// and a sweep of n_traj trajectories would use it (the launch shape follows
+// n_traj as in plan_sweep).
 void prefetch_kernel(const rn_network* net, int32_t precision, int64_t n_traj);
 
 }  // namespace rn_internal
